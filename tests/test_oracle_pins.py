@@ -1,0 +1,536 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks one oracle function against a closed form, a hand-counted
+fixture, brute-force enumeration on tiny inputs, or an independent library
+routine, so that a dropped term, a wrong sign, a swapped index or a transposed
+operand in the oracle fails at least one of them.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_01439_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+
+def random_graph(n, p, rng):
+    A = (rng.random((n, n)) < p).astype(np.uint8)
+    A = np.triu(A, 1)
+    return (A + A.T).astype(np.uint8)
+
+
+def brute_triangles(C):
+    n = C.shape[0]
+    return [(a, b, c) for a, b, c in itertools.combinations(range(n), 3)
+            if C[a, b] and C[a, c] and C[b, c]]
+
+
+def load_e1():
+    edges, piv, cl, meta = [], [], [], {}
+    with open(os.path.join(GOLDEN, "app_e1_graph.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].split()
+            if not line:
+                continue
+            if line[0] == "edge":
+                edges.append(tuple(map(int, line[1:])))
+            elif line[0] == "pivot":
+                piv.append(tuple(map(int, line[1:])))
+            elif line[0] == "clique":
+                cl.append(tuple(map(int, line[1:])))
+            else:
+                meta[line[0]] = int(line[1])
+    return meta, edges, piv, cl
+
+
+def small_pair(n=60, ratio=0.5, seed=1, **kw):
+    cfg = synth.CONFIGS["indoor_n1000"].replace(n=n, inlier_ratio=ratio, **kw)
+    return synth.make_pair(cfg, seed)
+
+
+# ---------------------------------------------------------------- Eq. 1
+
+def test_compat_closed_form_boundary_is_inclusive():
+    # |x_i - x_j| = 5 exactly (3-4-5), |y_i - y_j| = 5.25 exactly: delta = 0.25 exactly.
+    X = np.array([[0, 0, 0], [3, 4, 0]], np.float32)
+    Y = np.array([[0, 0, 0], [0, 0, 5.25]], np.float32)
+    C, b32, _, _ = oracle.compat(X, Y, 0.25)
+    assert C.tolist() == [[0, 1], [1, 0]]          # Eq. 1 uses "<=": delta == tau is compatible
+    assert b32 == 1
+    below = float(np.nextafter(np.float32(0.25), np.float32(0)))
+    C2, _, _, _ = oracle.compat(X, Y, below)
+    assert C2.tolist() == [[0, 0], [0, 0]]
+
+
+def test_compat_each_coordinate_counts():
+    # Only the z coordinate differs between the two lengths: a dropped z term passes x,y checks only.
+    X = np.array([[1, 2, 3], [1, 2, 3 + 4]], np.float32)        # |d| = 4
+    Y = np.array([[0, 0, 0], [0, 0, 4.5]], np.float32)          # |d| = 4.5
+    assert oracle.compat(X, Y, 0.49)[0][0, 1] == 0
+    assert oracle.compat(X, Y, 0.5)[0][0, 1] == 1
+    # lengths from x vs from y: swapping source and target must not matter (|a-b| symmetric)
+    assert np.array_equal(oracle.compat(Y, X, 0.49)[0], oracle.compat(X, Y, 0.49)[0])
+
+
+def test_compat_matches_float64_brute_force_off_boundary():
+    rng = np.random.default_rng(3)
+    p = small_pair(n=120, ratio=0.3, seed=5)
+    X, Y = p.src, p.dst
+    tau = 0.1
+    C, _, b64, flips = oracle.compat(X, Y, tau)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    dx = np.linalg.norm(X64[:, None] - X64[None], axis=2)
+    dy = np.linalg.norm(Y64[:, None] - Y64[None], axis=2)
+    delta = np.abs(dx - dy)
+    ref = (delta <= tau).astype(np.uint8)
+    np.fill_diagonal(ref, 0)
+    far = np.abs(delta - tau) > 1e-5
+    assert np.array_equal(C[far], ref[far])
+    iu = np.triu_indices(len(X), 1)
+    assert b64 == int((np.abs(delta[iu] - tau) < 1e-6).sum())
+    assert np.array_equal(C, C.T) and not C.diagonal().any()
+    assert rng is not None
+
+
+def test_compat_noiseless_rigid_copy_all_compatible():
+    # A rigid motion preserves lengths: every pair is compatible at a tiny tau.
+    p = small_pair(n=50, ratio=1.0, seed=7, sigma=0.0)
+    C, _, _, _ = oracle.compat(p.src, p.dst, 1e-4)
+    assert C.sum() == 50 * 49
+    # and a pure outlier set at a tiny tau has (almost) no edges
+    q = small_pair(n=50, ratio=0.0, seed=8)
+    assert oracle.compat(q.src, q.dst, 1e-4)[0].sum() == 0
+
+
+# ---------------------------------------------------------------- Eq. 2 / Appendix B
+
+def test_sc2_equals_triangle_count_brute_force():
+    rng = np.random.default_rng(11)
+    for n, p in [(5, 0.6), (17, 0.4), (33, 0.3), (40, 0.7)]:
+        C = random_graph(n, p, rng)
+        G = oracle.sc2(C)
+        ref = np.zeros((n, n), np.int64)
+        for a, b, c in brute_triangles(C):
+            for u, v in ((a, b), (a, c), (b, c)):
+                ref[u, v] += 1
+                ref[v, u] += 1
+        assert np.array_equal(G, ref)
+
+
+def test_sc2_complete_graph_closed_form():
+    for n in (3, 4, 9, 70, 130):
+        C = np.ones((n, n), np.uint8) - np.eye(n, dtype=np.uint8)
+        G = oracle.sc2(C)
+        off = ~np.eye(n, dtype=bool)
+        assert (G[off] == n - 2).all() and (G.diagonal() == 0).all()
+    # one edge, nothing else: weight 0
+    C = np.zeros((4, 4), np.uint8)
+    C[0, 1] = C[1, 0] = 1
+    assert oracle.sc2(C).sum() == 0
+
+
+def test_sc2_matches_dense_matmul_library():
+    rng = np.random.default_rng(12)
+    C = random_graph(300, 0.2, rng)
+    Cf = C.astype(np.float64)
+    ref = (Cf @ Cf) * Cf                         # exact in float64 for these sizes
+    assert np.array_equal(oracle.sc2(C), ref.astype(np.int32))
+
+
+def test_app_e1_graph_golden():
+    meta, edges, piv, cl = load_e1()
+    n = meta["n"]
+    C = np.zeros((n, n), np.uint8)
+    for i, j, _ in edges:
+        C[i, j] = C[j, i] = 1
+    G = oracle.sc2(C)
+    for i, j, w in edges:
+        assert G[i, j] == w and G[j, i] == w
+    assert G.sum() // 6 == meta["triangles"] == len(brute_triangles(C))
+    Gt = oracle.o2graph(G)
+    P, npv = oracle.pivots(Gt, meta["k1"])
+    assert npv == 3 and [tuple(r) for r in P] == piv
+    out = oracle.cliques(Gt, P, npv, meta["k1"], meta["k2"])
+    assert [tuple(r) for r in out] == cl
+
+
+# ---------------------------------------------------------------- Definition 2 / Eq. 4
+
+def test_o2graph_upper_triangle():
+    rng = np.random.default_rng(2)
+    G = rng.integers(0, 9, (6, 6)).astype(np.int32)
+    Gt = oracle.o2graph(G)
+    assert np.array_equal(Gt, np.triu(G, 1))
+
+
+def test_pivots_match_full_sort_with_heavy_ties():
+    rng = np.random.default_rng(4)
+    for n, k1 in [(12, 5), (30, 100), (30, 435), (30, 500), (25, 1)]:
+        W = rng.integers(0, 4, (n, n)).astype(np.int32)      # many ties
+        W = np.triu(W, 1)
+        P, npv = oracle.pivots(W, k1)
+        allp = sorted(((-int(W[i, j]), i, j) for i in range(n) for j in range(i + 1, n)))
+        ref = [(i, j, -w) for w, i, j in allp[:k1]]
+        assert npv == min(k1, n * (n - 1) // 2)
+        assert [tuple(r) for r in P[:npv]] == ref
+        assert (P[npv:, :2] == -1).all()
+
+
+# ---------------------------------------------------------------- Eqs. 5-8, Appendix C
+
+def brute_cliques(G, P, npv, k1, k2, directed=True):
+    n = G.shape[0]
+    out = np.full((k1 * k2, 3), -1, np.int64)
+    for p in range(k1):
+        if p >= npv:
+            continue
+        i, j = int(P[p, 0]), int(P[p, 1])
+        cand = []
+        for z in range(n):
+            if z in (i, j):
+                continue
+            if G[i, j] > 0 and G[i, z] > 0 and G[j, z] > 0:
+                cand.append((-(int(G[i, j]) + int(G[i, z]) + int(G[j, z])), z))
+        cand.sort()
+        for s in range(k2):
+            out[s * k1 + p] = (i, j, cand[s][1] if s < len(cand) else -1)
+    return out
+
+
+def test_cliques_match_brute_force():
+    rng = np.random.default_rng(6)
+    for n, pe, k1, k2, graph in [(20, 0.5, 8, 2, 0), (35, 0.3, 40, 3, 0), (30, 0.4, 12, 2, 1)]:
+        C = random_graph(n, pe, rng)
+        G = oracle.sc2(C)
+        Gb = oracle.o2graph(G) if graph == 0 else G
+        P, npv = oracle.pivots(Gb, k1)
+        got = oracle.cliques(Gb, P, npv, k1, k2)
+        assert np.array_equal(got, brute_cliques(Gb, P, npv, k1, k2))
+        for i, j, z in got:
+            if z >= 0:
+                assert C[i, j] and C[i, z] and C[j, z]      # every valid clique is a triangle of G
+
+
+def test_unique_assignment_property():
+    # With every pair a pivot and room for every third vertex, the O2Graph search
+    # emits each triangle of G exactly once (Appendix C).
+    rng = np.random.default_rng(9)
+    for n, pe in [(16, 0.5), (28, 0.35)]:
+        C = random_graph(n, pe, rng)
+        Gt = oracle.o2graph(oracle.sc2(C))
+        k1 = n * (n - 1) // 2
+        P, npv = oracle.pivots(Gt, k1)
+        cl = oracle.cliques(Gt, P, npv, k1, n)
+        found = sorted(tuple(sorted(r)) for r in cl if r[2] >= 0)
+        assert found == sorted(brute_triangles(C))
+        # the undirected SC2 graph finds every triangle three times
+        G = oracle.sc2(C)
+        cl_u = oracle.cliques(G, P, npv, k1, n)
+        found_u = sorted(tuple(sorted(r)) for r in cl_u if r[2] >= 0)
+        assert len(found_u) == 3 * len(found) and sorted(set(found_u)) == found
+
+
+def test_zero_weight_pivot_gives_no_clique():
+    # a pair that is not an edge but shares neighbours must not form a clique (Eq. 8 needs G_ij > 0)
+    C = np.zeros((4, 4), np.uint8)
+    for a, b in [(0, 2), (1, 2), (0, 3), (1, 3), (2, 3)]:
+        C[a, b] = C[b, a] = 1
+    G = oracle.sc2(C)
+    P = np.array([[0, 1, 0]], np.int32)
+    cl = oracle.cliques(G, P, 1, 1, 2)
+    assert (cl[:, 2] == -1).all()
+
+
+# ---------------------------------------------------------------- Section 3.5 Kabsch
+
+def numpy_kabsch(p, q):
+    pb, qb = p.mean(0), q.mean(0)
+    H = (p - pb).T @ (q - qb)
+    U, S, Vt = np.linalg.svd(H)
+    d = np.sign(np.linalg.det(Vt.T @ U.T)) or 1.0
+    R = Vt.T @ np.diag([1, 1, d]) @ U.T
+    return R, qb - R @ pb
+
+
+def horn_quaternion(p, q):
+    """Horn (1987) closed-form absolute orientation by unit quaternions."""
+    pb, qb = p.mean(0), q.mean(0)
+    M = (p - pb).T @ (q - qb)
+    Sxx, Sxy, Sxz = M[0]
+    Syx, Syy, Syz = M[1]
+    Szx, Szy, Szz = M[2]
+    N = np.array([
+        [Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx],
+        [Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz],
+        [Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy],
+        [Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz]])
+    w, V = np.linalg.eigh(N)
+    q0, qx, qy, qz = V[:, -1]
+    R = np.array([
+        [q0 * q0 + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - q0 * qz), 2 * (qx * qz + q0 * qy)],
+        [2 * (qy * qx + q0 * qz), q0 * q0 - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - q0 * qx)],
+        [2 * (qz * qx - q0 * qy), 2 * (qz * qy + q0 * qx), q0 * q0 - qx * qx - qy * qy + qz * qz]])
+    return R, qb - R @ pb
+
+
+def test_kabsch_noiseless_recovery_and_libraries():
+    rng = np.random.default_rng(21)
+    n = 30
+    X = (rng.random((n, 3)) - 0.5) * 3
+    R0 = synth.random_rotation(rng)
+    t0 = rng.standard_normal(3)
+    Y = X @ R0.T + t0
+    Xf, Yf = X.astype(np.float32), Y.astype(np.float32)
+    cl = np.array([rng.choice(n, 3, replace=False) for _ in range(40)], np.int32)
+    R, t, fl = oracle.kabsch(Xf, Yf, cl)
+    assert (fl == 1).all()
+    for h in range(len(cl)):
+        p = Xf[cl[h]].astype(np.float64)
+        q = Yf[cl[h]].astype(np.float64)
+        assert abs(np.linalg.det(R[h]) - 1) < 1e-12
+        assert np.abs(R[h].T @ R[h] - np.eye(3)).max() < 1e-12
+        Rn, tn = numpy_kabsch(p, q)
+        Rh, th = horn_quaternion(p, q)
+        assert np.abs(R[h] - Rn).max() < 1e-9 and np.abs(t[h] - tn).max() < 1e-9
+        assert np.abs(R[h] - Rh).max() < 1e-9 and np.abs(t[h] - th).max() < 1e-9
+        # float32 rounding of the inputs aside, the known motion comes back (Appendix A.3)
+        assert np.abs(R[h] - R0).max() < 1e-5 and np.abs(t[h] - t0).max() < 1e-5
+    # exact congruent triangle (inputs exactly representable): recovered to float64 precision
+    p = np.array([[0, 0, 0], [1, 0, 0], [0, 2, 0]], np.float32)
+    Rz = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]], np.float64)   # 90 degrees about z
+    q = (p.astype(np.float64) @ Rz.T + [1, 2, 3]).astype(np.float32)
+    R, t, fl = oracle.kabsch(p, q, np.array([[0, 1, 2]], np.int32))
+    assert np.abs(R[0] - Rz).max() < 1e-14 and np.abs(t[0] - [1, 2, 3]).max() < 1e-14
+
+
+def test_kabsch_reflection_and_degenerate():
+    rng = np.random.default_rng(22)
+    # noisy, random triplets: numpy agreement, proper rotation (no reflection)
+    X = rng.standard_normal((3, 3)).astype(np.float32)
+    Y = rng.standard_normal((3, 3)).astype(np.float32)
+    R, t, fl = oracle.kabsch(X, Y, np.array([[0, 1, 2]], np.int32))
+    Rn, tn = numpy_kabsch(X.astype(np.float64), Y.astype(np.float64))
+    assert abs(np.linalg.det(R[0]) - 1) < 1e-12 and np.abs(R[0] - Rn).max() < 1e-9
+    # collinear source points: flagged, still a rotation
+    Xc = np.array([[0, 0, 0], [1, 1, 1], [2, 2, 2]], np.float32)
+    R, t, fl = oracle.kabsch(Xc, Y, np.array([[0, 1, 2]], np.int32))
+    assert fl[0] == 2 and abs(np.linalg.det(R[0]) - 1) < 1e-12
+    # invalid clique
+    R, t, fl = oracle.kabsch(X, Y, np.array([[0, 1, -1]], np.int32))
+    assert fl[0] == 0 and np.array_equal(R[0], np.eye(3)) and not t.any()
+
+
+# ---------------------------------------------------------------- Eq. 9
+
+def test_score_matches_float64_count_off_boundary():
+    p = small_pair(n=400, ratio=0.3, seed=31)
+    rng = np.random.default_rng(31)
+    poses = []
+    for k in range(12):
+        R = p.R if k == 0 else synth.random_rotation(rng)
+        t = p.t if k == 0 else rng.standard_normal(3)
+        poses.append(np.concatenate([R.reshape(9), t]))
+    poses = np.array(poses, np.float32)
+    valid = np.ones(len(poses), np.int32)
+    valid[5] = 0
+    IN = oracle.score(p.src, p.dst, poses, valid, 0.1)
+    assert IN[5] == -1
+    for h in range(len(poses)):
+        if h == 5:
+            continue
+        R = poses[h, :9].astype(np.float64).reshape(3, 3)
+        t = poses[h, 9:].astype(np.float64)
+        r = np.linalg.norm(p.src.astype(np.float64) @ R.T + t - p.dst, axis=1)
+        assert abs(int((r <= 0.1).sum()) - IN[h]) <= int((np.abs(r - 0.1) < 1e-5).sum())
+    # under the true pose every inlier (sigma = 1 cm, 10 sigma threshold) is counted
+    assert IN[0] >= p.labels.sum()
+    m = oracle.mask(p.src, p.dst, poses[0], 0.1)
+    assert m.sum() == IN[0] and m[p.labels].all()
+
+
+def test_score_threshold_is_inclusive():
+    # identity pose, residuals 0.5 (exact) and 0.5 + 1 ulp: theta = 0.5 counts the first only
+    X = np.zeros((3, 3), np.float32)
+    Y = np.array([[0.5, 0, 0], [0, 0, np.nextafter(np.float32(0.5), np.float32(1))], [0, 0.3, 0.4]], np.float32)
+    pose = np.array([[1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0]], np.float32)
+    assert oracle.score(X, Y, pose, np.ones(1, np.int32), 0.5)[0] == 2
+    assert oracle.mask(X, Y, pose[0], 0.5).tolist() == [1, 0, 1]
+
+
+def test_select_lowest_index_on_ties():
+    assert oracle.select(np.array([-1, 3, 7, 7, 2], np.int32)) == 2
+    assert oracle.select(np.array([-1, -1], np.int32)) == -1
+    assert oracle.select(np.array([0, -1], np.int32)) == 0
+
+
+# ---------------------------------------------------------------- whole path
+
+def test_register_recovers_pose_indoor_small():
+    cfg = synth.CONFIGS["indoor_n1000"].replace(n=400, k1=100)
+    p = synth.make_pair(cfg, synth.pair_seed(0, 0))
+    r, m = oracle.register(p.src, p.dst, cfg.tau, cfg.theta, cfg.k1, cfg.k2)
+    assert r.status == 0
+    R = np.array(r.R).reshape(3, 3)
+    assert synth.rotation_error_deg(R, p.R) < 15 and synth.translation_error(np.array(r.t), p.t) < 0.3
+    assert m.sum() == r.best_inliers and r.best_inliers >= 0.9 * p.labels.sum()
+    assert r.n_pivots == cfg.k1
+
+
+def test_register_all_outliers_no_hypothesis():
+    X = np.array([[0, 0, 0], [10, 0, 0], [0, 20, 0], [0, 0, 40]], np.float32)
+    Y = np.array([[0, 0, 0], [1, 0, 0], [0, 3, 0], [0, 0, 7]], np.float32)
+    r, m = oracle.register(X, Y, 0.01, 0.01, 3, 2)
+    assert r.status == 3 and r.best_hyp == -1 and not m.any()
+    assert list(r.R) == [1, 0, 0, 0, 1, 0, 0, 0, 1]
+
+
+# ---------------------------------------------------------------- learned scorer
+
+def brute_features(X, Y, tau, C, G):
+    n = len(X)
+    X64, Y64 = X.astype(np.float32), Y.astype(np.float32)
+    F = np.zeros((n, 19))
+    q = np.float32(tau) * np.float32(0.25)
+    edges = [np.float32(k) * q for k in range(16)]
+    for a in range(n):
+        others = [b for b in range(n) if b != a]
+        F[a, 0] = C[a, others].sum() / (n - 1)
+        F[a, 1] = G[a, others].sum() / ((n - 1) * n)
+        F[a, 2] = G[a].max() / n
+        for b in others:
+            dx = np.float32(np.linalg.norm(X64[a].astype(np.float64) - X64[b]))
+            dy = np.float32(np.linalg.norm(Y64[a].astype(np.float64) - Y64[b]))
+            d = abs(dx - dy)
+            k = max(k for k in range(16) if d >= edges[k])
+            F[a, 3 + k] += 1.0 / (n - 1)
+    return F
+
+
+def test_features_brute_force():
+    p = small_pair(n=40, ratio=0.4, seed=41)
+    C, _, _, _ = oracle.compat(p.src, p.dst, 0.1)
+    G = oracle.sc2(C)
+    F = oracle.features(p.src, p.dst, 0.1, C, G)
+    ref = brute_features(p.src, p.dst, 0.1, C, G)
+    assert np.abs(F[:, :3] - ref[:, :3]).max() < 1e-15
+    # histogram: bins agree except where the float64 length rounds differently at a bin edge
+    assert np.abs(F[:, 3:] - ref[:, 3:]).sum() <= 4.0 / 39
+    assert np.allclose(F[:, 3:].sum(1), 1.0)
+
+
+def test_features_bin_edge_is_inclusive():
+    # delta = 0.25 exactly with tau = 1: bin edge e_1 = 0.25, so the pair lands in bin 1.
+    X = np.array([[0, 0, 0], [3, 4, 0], [100, 0, 0]], np.float32)
+    Y = np.array([[0, 0, 0], [0, 0, 5.25], [0, 300, 0]], np.float32)
+    C, _, _, _ = oracle.compat(X, Y, 1.0)
+    G = oracle.sc2(C)
+    F = oracle.features(X, Y, 1.0, C, G)
+    assert F[0, 3 + 1] == 0.5 and F[0, 3 + 0] == 0.0 and F[0, 3 + 15] == 0.5
+    assert F[0, 0] == 0.5 and F[2, 0] == 0.0
+
+
+def rand_weights(rng, scale=0.3, bf16=False):
+    shapes = [(64, 19), (64,), (64, 64), (64,), (1, 64), (1,)]
+    ws = [rng.standard_normal(s) * scale for s in shapes]
+    if bf16:
+        ws = [np.vectorize(oracle.bf16_round)(w).astype(np.float64) for w in ws]
+    return ws
+
+
+def test_gelu_and_mlp_closed_forms():
+    # zero weights: s = b3 for every sample
+    rng = np.random.default_rng(51)
+    F = rng.random((5, 19))
+    ws = [np.zeros((64, 19)), np.zeros(64), np.zeros((64, 64)), np.zeros(64), np.zeros((1, 64)), np.array([0.75])]
+    assert np.allclose(oracle.mlp_fwd(F, ws), 0.75)
+    # one path: W1 e_0 -> unit 0, W2 unit0 -> unit0, W3 reads unit 0: s = gelu(gelu(x0))
+    ws = [np.zeros((64, 19)), np.zeros(64), np.zeros((64, 64)), np.zeros(64), np.zeros((1, 64)), np.zeros(1)]
+    ws[0][0, 0] = 1.0
+    ws[2][0, 0] = 1.0
+    ws[4][0, 0] = 1.0
+    F = np.zeros((3, 19))
+    F[:, 0] = [0.0, 3.0, -3.0]
+
+    def gelu(x):
+        return 0.5 * x * (1 + math.tanh(math.sqrt(2 / math.pi) * (x + 0.044715 * x ** 3)))
+    s = oracle.mlp_fwd(F, ws)
+    ref = [oracle.bf16_round(gelu(oracle.bf16_round(gelu(x)))) for x in F[:, 0]]
+    assert np.allclose(s, ref, rtol=0, atol=1e-12)
+    assert s[0] == 0.0
+
+
+def test_mlp_backward_finite_differences():
+    rng = np.random.default_rng(52)
+    F = rng.random((16, 19))
+    y = (rng.random(16) < 0.4).astype(np.uint8)
+    ws = rand_weights(rng)
+    loss, grads = oracle.mlp_bwd(F, y, ws, exact=True)
+    eps = 1e-6
+    for wi, (w, g) in enumerate(zip(ws, grads)):
+        flat = w.reshape(-1)
+        idx = rng.choice(flat.size, min(flat.size, 12), replace=False)
+        for k in idx:
+            old = flat[k]
+            flat[k] = old + eps
+            lp, _ = oracle.mlp_bwd(F, y, ws, exact=True)
+            flat[k] = old - eps
+            lm, _ = oracle.mlp_bwd(F, y, ws, exact=True)
+            flat[k] = old
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - g.reshape(-1)[k]) < 1e-7 + 1e-5 * abs(fd), (wi, k)
+    # BCE closed form at s = b3 with zero weights: loss = log(1 + e^{-b}) for y = 1
+    z = [np.zeros((64, 19)), np.zeros(64), np.zeros((64, 64)), np.zeros(64), np.zeros((1, 64)), np.array([0.3])]
+    l1, g1 = oracle.mlp_bwd(F[:1], np.array([1], np.uint8), z, exact=True)
+    assert abs(l1 - math.log1p(math.exp(-0.3))) < 1e-15
+    assert abs(g1[5][0] - (1 / (1 + math.exp(-0.3)) - 1)) < 1e-15
+
+
+def test_adam_first_step_closed_form():
+    w = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    oracle.adam(w, g, m, v, 1, 0.01, eps=0.0)
+    # after one step the bias-corrected moments are g and g^2: the update is lr * sign(g)
+    assert np.allclose(w, [0.99, -1.99, 0.49], rtol=0, atol=1e-15)
+
+
+def test_bf16_rounding_known_values():
+    assert oracle.bf16_round(1.0) == 1.0
+    assert oracle.bf16_round(1 + 2 ** -8) == 1.0                    # tie -> even
+    assert oracle.bf16_round(1 + 3 * 2 ** -8) == 1 + 2 ** -6         # tie -> even (up)
+    assert oracle.bf16_round(1 + 2 ** -8 + 2 ** -12) == 1 + 2 ** -7  # above the tie
+    assert math.isnan(oracle.bf16_round(float("nan")))
+
+
+def test_learned_pivots_order_and_fallback():
+    P = np.array([[0, 1, 9], [2, 3, 8], [4, 5, 8], [6, 7, 1]], np.int32)
+    s = np.array([0, 0, 1, 1, 5, 5, 0.5, 0.5], np.float32)
+    out, fb = oracle.pivots_learned(P, s, 3)
+    assert not fb and out[:, :2].tolist() == [[4, 5], [2, 3], [6, 7]]
+    s2 = np.array([1, 1, 1, 1, 1, 1, 1, 1], np.float32)
+    out, fb = oracle.pivots_learned(P, s2, 2)                          # all tied: plain order
+    assert out[:, :2].tolist() == [[0, 1], [2, 3]]
+    s3 = s.copy()
+    s3[3] = np.nan
+    out, fb = oracle.pivots_learned(P, s3, 2)
+    assert fb and out[:, :2].tolist() == [[0, 1], [2, 3]]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_generator_statistics(seed):
+    cfg = synth.CONFIGS["indoor_n5000"]
+    p = synth.make_pair(cfg, synth.pair_seed(1, seed))
+    assert p.src.dtype == np.float32 and p.src.shape == (5000, 3)
+    assert p.labels.sum() == 250
+    assert np.abs(p.src).max() <= 1.5
+    res = p.dst[p.labels].astype(np.float64) - (p.src[p.labels].astype(np.float64) @ p.R.T + p.t)
+    assert 0.015 < res.std() < 0.025
+    assert abs(np.linalg.det(p.R) - 1) < 1e-12 and np.linalg.norm(p.t) <= 1.0
