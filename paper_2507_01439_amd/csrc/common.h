@@ -1,0 +1,107 @@
+// Internal declarations shared by the HIP sources of libturboreg (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/turboreg.h"
+
+namespace tr {
+
+constexpr int kSc2Tile = 128;     // output tile edge of the int8 MFMA SC2 kernel; npad is a multiple
+constexpr int kCompatTile = 64;   // tile edge of the compatibility kernel
+constexpr int kRowsPerItem = 16;  // rows per work item of the pivot scans
+constexpr int kPrepRows = 256;    // rows per work item of the prep kernel
+constexpr int kScoreHyp = 256;    // hypotheses per scoring work item (one per thread)
+constexpr int kScorePts = 128;    // points per scoring work item
+
+// Work-list stages whose per-pair item counts depend on N_b; each has a
+// prefix array of B+1 entries in Plan::pre.
+enum Stage { kPrep = 0, kCompat, kSc2, kRowBlk, kScore, kNumPrefix };
+
+struct PairDesc {
+    int32_t n;        // matches in this pair (0 when the pair is invalid)
+    int32_t npad;     // n rounded up to kSc2Tile
+    int32_t pt_off;   // first match of this pair in src/dst
+    int32_t kpiv;     // pivots to select: min(k1 or pool, n(n-1)/2)
+    int64_t c_off;    // byte offset of this pair's C in the C arena (npad x npad int8)
+    int64_t g_off;    // element offset of this pair's G in the G arena (npad x npad uint16)
+};
+
+// Per-pair scalars written by the kernels.
+struct PairState {
+    int32_t status;     // tr_status
+    int32_t nonfinite;  // 1 if any coordinate is NaN/Inf
+    int32_t n_boundary;
+    int32_t n_edges;
+    int32_t alpha;      // weight of the last pivot (the K-th largest, Eq. 4)
+    int32_t c_gt;       // edges heavier than alpha (all selected)
+    int32_t m_eq;       // edges of weight alpha to take, in lexicographic order
+    int32_t fallback;   // learned scores were not finite
+};
+
+struct Plan {
+    int32_t B;
+    int32_t total[kNumPrefix];
+};
+
+// Device views passed to every kernel.
+struct Work {
+    const float *src, *dst;
+    const PairDesc *pairs;
+    PairState *state;
+    const Plan *plan;
+    const int32_t *pre;       // kNumPrefix x (max_batch + 1)
+    int32_t pre_stride;       // max_batch + 1
+    int32_t max_n;            // per-pair row stride of the per-row arenas
+    int32_t k1, k2, pool;     // pool = plain pivots selected (k1, or pool_factor*k1 in learned mode)
+    int32_t H;                // k1 * k2 hypotheses per pair
+    int32_t graph;
+    float tau, theta;
+    uint8_t *C;               // C arena
+    uint16_t *G;              // G arena
+    int32_t *hist;            // max_batch x max_n weight histogram
+    int32_t *rowcnt;          // max_batch x max_n x 2 (count > alpha, count == alpha)
+    int32_t *blkcnt;          // max_batch x nblk x 2
+    int32_t nblk_stride;      // blocks of kRowsPerItem rows per pair (for max_n)
+    uint64_t *cand;           // max_batch x pool_cap selection candidates (sort keys)
+    int32_t pool_cap;
+    int32_t *pivots_plain;    // max_batch x pool_cap x 3
+    int32_t *pivots;          // pivots the clique search uses: max_batch x piv_stride x 3
+    int32_t piv_stride;       // pool_cap in plain mode (pivots == pivots_plain), k1_cap in learned mode
+    int32_t *cliques;         // max_batch x h_cap x 3
+    float *poses;             // max_batch x h_cap x 12
+    int32_t *inl;             // max_batch x h_cap
+    int32_t h_cap;
+    int32_t *rowstat;         // max_batch x max_n x 20 feature accumulators (learned mode)
+    uint16_t *feat;           // max_batch x max_n x 19 bfloat16 features
+    float *scores;            // max_batch x max_n learned scores
+    tr_result *out;
+    uint8_t *masks;           // nullable; pair b's mask starts at pairs[b].pt_off
+    int32_t learned;          // learned pivot mode / feature accumulation on
+};
+
+// Largest b in [0, B) with pre[b] <= item (pre is non-decreasing, pre[0] = 0).
+__device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- launchers (one per kernel family); each returns the launch's hipError_t ----
+hipError_t launch_plan(const Work &w, const int32_t *offsets, int32_t n_single, int32_t B,
+                       int32_t max_n, PairDesc *pairs, PairState *state, Plan *plan, int32_t *pre,
+                       hipStream_t s);
+hipError_t launch_prep(const Work &w, int grid, hipStream_t s);
+hipError_t launch_compat(const Work &w, int grid, hipStream_t s);
+hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
+hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
+hipError_t launch_cliques(const Work &w, int B, hipStream_t s);
+hipError_t launch_kabsch(const Work &w, int B, hipStream_t s);
+hipError_t launch_score(const Work &w, int grid, hipStream_t s);
+hipError_t launch_select(const Work &w, int B, hipStream_t s);
+
+}  // namespace tr

@@ -1,0 +1,379 @@
+// Hypothesis generation and scoring on gfx950: TurboClique search with
+// top-K2 selection (Eqs. 5-8, Algorithms 1-2), one rigid fit per clique
+// (Section 3.5), inlier numbers (Eq. 9) and the final argmax.
+#include "common.h"
+
+namespace tr {
+namespace {
+
+// ---------------------------------------------------------------- Eqs. 5-8
+
+// Candidate key: larger S first, then smaller z. Zero means "empty".
+__device__ __forceinline__ uint64_t clique_key(uint32_t S, uint32_t z)
+{
+    return ((uint64_t)S << 32) | (uint64_t)(0xFFFFFFFFu - z);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// One wavefront per pivot. Lanes stride over the third vertex z; each keeps
+// its KMAX best keys sorted in registers (insertion by compare-and-swap, no
+// dynamic register indexing), then K2 rounds of a wave-wide max pick the
+// pivot's cliques in (S desc, z asc) order.
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_cliques(Work w, int total)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave0 = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
+    for (int item = wave0; item < total; item += nwaves) {
+        const int b = item / w.k1, p = item - b * w.k1;
+        const PairDesc d = w.pairs[b];
+        const int32_t *pv = w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
+        const int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
+        int32_t *cl = w.cliques + (int64_t)b * w.h_cap * 3;
+        uint64_t top[KMAX];
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) top[s] = 0;
+        if (i >= 0) {
+            const uint16_t *G = w.G + d.g_off;
+            const int64_t npad = d.npad;
+            const int wij = i < j ? G[i * npad + j] : G[(int64_t)j * npad + i];
+            if (wij > 0) {
+                const int z0 = w.graph == TR_GRAPH_O2 ? j + 1 : 0;
+                for (int z = z0 + lane; z < d.n; z += 64) {
+                    int giz, gjz;
+                    if (w.graph == TR_GRAPH_O2) {
+                        giz = G[i * npad + z];
+                        gjz = G[(int64_t)j * npad + z];
+                    } else {
+                        if (z == i || z == j) continue;
+                        giz = i < z ? G[i * npad + z] : G[(int64_t)z * npad + i];
+                        gjz = j < z ? G[(int64_t)j * npad + z] : G[(int64_t)z * npad + j];
+                    }
+                    if (giz > 0 && gjz > 0) {
+                        uint64_t k = clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z);
+#pragma unroll
+                        for (int s = 0; s < KMAX; ++s) {
+                            const uint64_t t = top[s];
+                            const bool gt = k > t;
+                            top[s] = gt ? k : t;
+                            k = gt ? t : k;
+                        }
+                    }
+                }
+            }
+        }
+        for (int s = 0; s < w.k2; ++s) {
+            const uint64_t best = wave_max_u64(top[0]);
+            if (best != 0 && top[0] == best) {          // keys are unique per z: one owner
+#pragma unroll
+                for (int q = 0; q + 1 < KMAX; ++q) top[q] = top[q + 1];
+                top[KMAX - 1] = 0;
+            }
+            if (lane == 0) {
+                const int64_t h = (int64_t)s * w.k1 + p;
+                cl[3 * h] = i;
+                cl[3 * h + 1] = j;
+                cl[3 * h + 2] = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)best) : -1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- Section 3.5
+
+// One Jacobi rotation of the symmetric 4x4 A (and the eigenvector matrix V)
+// that zeroes A[p][q].
+template <int p, int q>
+__device__ __forceinline__ void jacobi_rot(double (&A)[4][4], double (&V)[4][4])
+{
+    const double apq = A[p][q];
+    if (apq == 0.0) return;
+    const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double akp = A[k][p], akq = A[k][q];
+        A[k][p] = c * akp - s * akq;
+        A[k][q] = s * akp + c * akq;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double apk = A[p][k], aqk = A[q][k];
+        A[p][k] = c * apk - s * aqk;
+        A[q][k] = s * apk + c * aqk;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - s * vkq;
+        V[k][q] = s * vkp + c * vkq;
+    }
+}
+
+// Least-squares rotation of three matches by Horn's unit-quaternion method
+// (J. Opt. Soc. Am. A 4(4), 1987): the rotation maximising sum (R p_a).q_a on
+// centred points is the eigenvector of the largest eigenvalue of a symmetric
+// 4x4 matrix built from M = sum p_a q_a^T. Solved in float64 by cyclic Jacobi,
+// then rounded to float32. One thread per hypothesis; IN is initialised here.
+__global__ void __launch_bounds__(256) k_kabsch(Work w, int total)
+{
+    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
+        const int b = item / w.H, h = item - b * w.H;
+        const PairDesc d = w.pairs[b];
+        const int32_t *c = w.cliques + ((int64_t)b * w.h_cap + h) * 3;
+        float *pose = w.poses + ((int64_t)b * w.h_cap + h) * 12;
+        int32_t *inl = w.inl + (int64_t)b * w.h_cap + h;
+        const int ia = c[0], ib = c[1], ic = c[2];
+        if (d.n == 0 || ic < 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) pose[k] = (k < 9 && k % 4 == 0) ? 1.0f : 0.0f;
+            *inl = -1;
+            continue;
+        }
+        const int idx[3] = {ia, ib, ic};
+        double P[3][3], Q[3][3], pb[3] = {0, 0, 0}, qb[3] = {0, 0, 0};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                P[a][k] = w.src[3 * (int64_t)(d.pt_off + idx[a]) + k];
+                Q[a][k] = w.dst[3 * (int64_t)(d.pt_off + idx[a]) + k];
+                pb[k] += P[a][k];
+                qb[k] += Q[a][k];
+            }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { pb[k] /= 3.0; qb[k] /= 3.0; }
+        double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int s = 0; s < 3; ++s) M[r][s] += (P[a][r] - pb[r]) * (Q[a][s] - qb[s]);
+        const double Sxx = M[0][0], Sxy = M[0][1], Sxz = M[0][2], Syx = M[1][0], Syy = M[1][1], Syz = M[1][2],
+                     Szx = M[2][0], Szy = M[2][1], Szz = M[2][2];
+        double A[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+                          {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
+                          {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
+                          {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
+        double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+        double scale = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) scale += A[r][s] * A[r][s];
+        for (int sweep = 0; sweep < 16; ++sweep) {
+            const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[0][3] * A[0][3] + A[1][2] * A[1][2] +
+                               A[1][3] * A[1][3] + A[2][3] * A[2][3];
+            if (off <= 1e-30 * scale) break;
+            jacobi_rot<0, 1>(A, V);
+            jacobi_rot<0, 2>(A, V);
+            jacobi_rot<0, 3>(A, V);
+            jacobi_rot<1, 2>(A, V);
+            jacobi_rot<1, 3>(A, V);
+            jacobi_rot<2, 3>(A, V);
+        }
+        int best = 0;
+        double bv = A[0][0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (A[k][k] > bv) { bv = A[k][k]; best = k; }
+        double q0 = V[0][0], qx = V[1][0], qy = V[2][0], qz = V[3][0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (best == k) { q0 = V[0][k]; qx = V[1][k]; qy = V[2][k]; qz = V[3][k]; }
+        const double nq = 1.0 / sqrt(q0 * q0 + qx * qx + qy * qy + qz * qz);
+        q0 *= nq; qx *= nq; qy *= nq; qz *= nq;
+        const double R[9] = {q0 * q0 + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - q0 * qz), 2 * (qx * qz + q0 * qy),
+                             2 * (qy * qx + q0 * qz), q0 * q0 - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - q0 * qx),
+                             2 * (qz * qx - q0 * qy), 2 * (qz * qy + q0 * qx), q0 * q0 - qx * qx - qy * qy + qz * qz};
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pose[k] = (float)R[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            pose[9 + r] = (float)(qb[r] - (R[3 * r] * pb[0] + R[3 * r + 1] * pb[1] + R[3 * r + 2] * pb[2]));
+        *inl = 0;
+    }
+}
+
+// ---------------------------------------------------------------- Eq. 9
+
+// Residual |R x + t - y|^2 in float32 with the pinned operation order: each
+// component starts at t and adds the three products by fused multiply-adds;
+// the squared norm rounds the first square and fuses the other two.
+__device__ __forceinline__ float residual2(const float (&ps)[12], float x0, float x1, float x2, float y0, float y1,
+                                           float y2)
+{
+    float u = ps[9];
+    u = __builtin_fmaf(ps[0], x0, u);
+    u = __builtin_fmaf(ps[1], x1, u);
+    u = __builtin_fmaf(ps[2], x2, u);
+    const float rx = u - y0;
+    float v = ps[10];
+    v = __builtin_fmaf(ps[3], x0, v);
+    v = __builtin_fmaf(ps[4], x1, v);
+    v = __builtin_fmaf(ps[5], x2, v);
+    const float ry = v - y1;
+    float z = ps[11];
+    z = __builtin_fmaf(ps[6], x0, z);
+    z = __builtin_fmaf(ps[7], x1, z);
+    z = __builtin_fmaf(ps[8], x2, z);
+    const float rz = z - y2;
+    float s = rx * rx;
+    s = __builtin_fmaf(ry, ry, s);
+    s = __builtin_fmaf(rz, rz, s);
+    return s;
+}
+
+// Work item = 256 hypotheses x kScorePts matches of one pair. Each thread
+// holds one pose in registers and walks the matches staged in LDS (every lane
+// reads the same address: an LDS broadcast). Partial counts go to IN with one
+// integer atomic per thread, so the result does not depend on the order.
+__global__ void __launch_bounds__(256) k_score(Work w)
+{
+    __shared__ float sp[6][kScorePts];
+    const int total = w.plan->total[kScore], B = w.plan->B;
+    const int32_t *pre = w.pre + kScore * w.pre_stride;
+    const float th2 = w.theta * w.theta;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_pair(pre, B, item);
+        const PairDesc d = w.pairs[b];
+        const int npc = (d.n + kScorePts - 1) / kScorePts;
+        const int local = item - pre[b], hb = local / npc, pc = local - hb * npc;
+        const int k0 = pc * kScorePts, cnt = min(kScorePts, d.n - k0);
+        for (int t = threadIdx.x; t < cnt * 6; t += 256) {
+            const int k = t / 6, f = t - k * 6;
+            const float *base = f < 3 ? w.src : w.dst;
+            sp[f][k] = base[3 * (int64_t)(d.pt_off + k0 + k) + (f % 3)];
+        }
+        __syncthreads();
+        const int h = hb * kScoreHyp + threadIdx.x;
+        int32_t *inl = w.inl + (int64_t)b * w.h_cap + h;
+        if (h < w.H && *inl >= 0) {
+            float ps[12];
+            const float *pose = w.poses + ((int64_t)b * w.h_cap + h) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) ps[k] = pose[k];
+            int c = 0;
+            for (int k = 0; k < cnt; ++k)
+                c += residual2(ps, sp[0][k], sp[1][k], sp[2][k], sp[3][k], sp[4][k], sp[5][k]) <= th2;
+            if (c) atomicAdd(inl, c);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- selection
+
+// One workgroup per pair: argmax of IN (lowest h on ties), result record and
+// the inlier mask under the selected pose.
+__global__ void __launch_bounds__(256) k_select(Work w)
+{
+    __shared__ uint64_t red[4];
+    __shared__ int32_t cnt[4];
+    const int b = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const PairDesc d = w.pairs[b];
+    const PairState st = w.state[b];
+    uint64_t best = 0;
+    int nvalid = 0;
+    if (d.n > 0) {
+        const int32_t *inl = w.inl + (int64_t)b * w.h_cap;
+        for (int h = threadIdx.x; h < w.H; h += 256) {
+            const int v = inl[h];
+            if (v >= 0) {
+                ++nvalid;
+                const uint64_t k = ((uint64_t)(v + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
+                best = k > best ? k : best;
+            }
+        }
+    }
+    best = wave_max_u64(best);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nvalid += __shfl_xor(nvalid, o, 64);
+    if (lane == 0) { red[wv] = best; cnt[wv] = nvalid; }
+    __syncthreads();
+    best = red[0];
+    nvalid = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    for (int k = 1; k < 4; ++k) best = red[k] > best ? red[k] : best;
+    const int hbest = best ? (int)(0xFFFFFFFFu - (uint32_t)best) : -1;
+    float ps[12];
+    if (hbest >= 0) {
+        const float *pose = w.poses + ((int64_t)b * w.h_cap + hbest) * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ps[k] = pose[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) ps[k] = (k < 9 && k % 4 == 0) ? 1.0f : 0.0f;
+    }
+    if (threadIdx.x == 0) {
+        tr_result r;
+        for (int k = 0; k < 9; ++k) r.R[k] = ps[k];
+        for (int k = 0; k < 3; ++k) r.t[k] = ps[9 + k];
+        r.best_inliers = hbest >= 0 ? (int32_t)(best >> 32) - 1 : 0;
+        r.best_hyp = hbest;
+        r.n_valid_hyp = nvalid;
+        int status = TR_OK;
+        if (st.status == TR_ERR_INVALID_ARG) status = TR_ERR_INVALID_ARG;
+        else if (st.nonfinite) status = TR_ERR_NONFINITE;
+        else if (hbest < 0) status = TR_ERR_NO_HYPOTHESIS;
+        else if (st.fallback) status = TR_WARN_SCORER_FALLBACK;
+        r.status = status;
+        r.n_boundary_pairs = st.n_boundary;
+        r.n_pivots = d.n > 0 ? min(w.k1, d.kpiv) : 0;
+        r.n_edges = st.n_edges;
+        r.reserved = 0;
+        w.out[b] = r;
+    }
+    if (w.masks && d.n > 0) {
+        const float th2 = w.theta * w.theta;
+        for (int k = threadIdx.x; k < d.n; k += 256) {
+            const int64_t g = d.pt_off + k;
+            const bool in = hbest >= 0 && residual2(ps, w.src[3 * g], w.src[3 * g + 1], w.src[3 * g + 2], w.dst[3 * g],
+                                                    w.dst[3 * g + 1], w.dst[3 * g + 2]) <= th2;
+            w.masks[g] = in ? 1 : 0;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cliques(const Work &w, int B, hipStream_t s)
+{
+    const int total = B * w.k1;
+    const int grid = min((total + 3) / 4, 4096);
+    if (w.k2 <= 2) hipLaunchKernelGGL(k_cliques<2>, dim3(grid), dim3(256), 0, s, w, total);
+    else hipLaunchKernelGGL(k_cliques<TR_MAX_K2>, dim3(grid), dim3(256), 0, s, w, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_kabsch(const Work &w, int B, hipStream_t s)
+{
+    const int total = B * w.H;
+    const int grid = min((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_kabsch, dim3(grid), dim3(256), 0, s, w, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_score(const Work &w, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_score, dim3(grid), dim3(256), 0, s, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const Work &w, int B, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_select, dim3(B), dim3(256), 0, s, w);
+    return hipGetLastError();
+}
+
+}  // namespace tr

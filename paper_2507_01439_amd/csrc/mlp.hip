@@ -1,0 +1,492 @@
+// Learned pivot scorer on gfx950: per-match features, a 19 -> 64 -> 64 -> 1
+// GELU MLP with bfloat16 weights and activations and float32 accumulation,
+// the learned pivot reorder with plain SC2 order as fallback, and the
+// training kernels (forward/backward, weight-gradient reduction, Adam).
+#include <vector>
+
+#include "mlp.h"
+
+namespace tr {
+namespace {
+
+constexpr float kGeluC = 0.7978845608028654f;   // sqrt(2/pi)
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
+
+// tanh-form GELU (Hendrycks & Gimpel 2016) and its derivative.
+__device__ __forceinline__ float gelu(float x)
+{
+    return 0.5f * x * (1.0f + tanhf(kGeluC * (x + 0.044715f * x * x * x)));
+}
+
+__device__ __forceinline__ float gelu_grad(float x)
+{
+    const float th = tanhf(kGeluC * (x + 0.044715f * x * x * x));
+    return 0.5f * (1.0f + th) + 0.5f * x * (1.0f - th * th) * kGeluC * (1.0f + 3.0f * 0.044715f * x * x);
+}
+
+// Parameters in LDS as float32: the weights are the bfloat16 copies, the biases the master values.
+struct MlpLds {
+    float p[TR_MLP_NPARAM];
+};
+
+__device__ void load_params(MlpLds &L, const uint16_t *wbf16, const float *w32)
+{
+    for (int k = threadIdx.x; k < TR_MLP_NPARAM; k += blockDim.x) {
+        const bool bias = (k >= kB1 && k < kW2) || (k >= kB2 && k < kW3) || k == kB3;
+        L.p[k] = bias ? w32[k] : bf2f(wbf16[k]);
+    }
+}
+
+// Forward pass of one sample (inference): float32 accumulation, bfloat16
+// activations. Layer 1 is fully unrolled so a1 stays in registers.
+__device__ float forward(const MlpLds &L, const float (&x)[19])
+{
+    float a1[64];
+#pragma unroll
+    for (int o = 0; o < 64; ++o) {
+        float acc = L.p[kB1 + o];
+#pragma unroll
+        for (int k = 0; k < 19; ++k) acc = __builtin_fmaf(L.p[kW1 + 19 * o + k], x[k], acc);
+        a1[o] = bfround(gelu(acc));
+    }
+    float s = L.p[kB3];
+#pragma unroll 2
+    for (int o = 0; o < 64; ++o) {
+        float acc = L.p[kB2 + o];
+#pragma unroll
+        for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(L.p[kW2 + 64 * o + k], a1[k], acc);
+        s = __builtin_fmaf(L.p[kW3 + o], bfround(gelu(acc)), s);
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------- features
+
+// 19 values per match from the integer accumulators (degree, SC2 row sum and
+// max, 16-bin delta histogram): ratios formed in float64, rounded to float32,
+// then to bfloat16.
+__global__ void __launch_bounds__(256) k_features(Work w, uint16_t *packed)
+{
+    const int total = w.plan->total[kPrep], B = w.plan->B;
+    const int32_t *pre = w.pre + kPrep * w.pre_stride;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_pair(pre, B, item);
+        const PairDesc d = w.pairs[b];
+        const int i = (item - pre[b]) * kPrepRows + threadIdx.x;
+        if (i >= d.n) continue;
+        const int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+        const double n1 = (double)(d.n - 1), n = (double)d.n;
+        uint16_t *f = packed ? packed + (int64_t)(d.pt_off + i) * 19 : w.feat + ((int64_t)b * w.max_n + i) * 19;
+        f[0] = f2bf((float)((double)rs[0] / n1));
+        f[1] = f2bf((float)((double)rs[1] / (n1 * n)));
+        f[2] = f2bf((float)((double)rs[2] / n));
+#pragma unroll
+        for (int k = 0; k < 16; ++k) f[3 + k] = f2bf((float)((double)rs[3 + k] / n1));
+    }
+}
+
+// ---------------------------------------------------------------- inference + reorder
+
+__global__ void __launch_bounds__(256) k_mlp_rows(Work w, const uint16_t *wbf16, const float *w32)
+{
+    __shared__ MlpLds L;
+    load_params(L, wbf16, w32);
+    __syncthreads();
+    const int total = w.plan->total[kPrep], B = w.plan->B;
+    const int32_t *pre = w.pre + kPrep * w.pre_stride;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_pair(pre, B, item);
+        const PairDesc d = w.pairs[b];
+        const int i = (item - pre[b]) * kPrepRows + threadIdx.x;
+        bool bad = false;
+        if (i < d.n) {
+            const uint16_t *f = w.feat + ((int64_t)b * w.max_n + i) * 19;
+            float x[19];
+#pragma unroll
+            for (int k = 0; k < 19; ++k) x[k] = bf2f(f[k]);
+            const float s = forward(L, x);
+            w.scores[(int64_t)b * w.max_n + i] = s;
+            bad = !isfinite(s);
+        }
+        if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&w.state[b].fallback, 1);
+    }
+}
+
+// Order the pool of plain pivots by e = s_i + s_j (desc), ties by plain rank,
+// keep the first K1. Non-finite scores anywhere in the pair: keep plain order.
+__global__ void __launch_bounds__(1024) k_reorder(Work w)
+{
+    extern __shared__ uint64_t keys[];
+    const int b = blockIdx.x;
+    const PairDesc d = w.pairs[b];
+    const int K = d.kpiv;
+    const bool fb = w.state[b].fallback != 0;
+    int P = 1;
+    while (P < K) P <<= 1;
+    const int32_t *pl = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
+    const float *sc = w.scores + (int64_t)b * w.max_n;
+    for (int r = threadIdx.x; r < P; r += 1024) {
+        uint64_t k = ~0ull;
+        if (r < K) {
+            uint32_t hi = 0;
+            if (!fb) {
+                const float e = (sc[pl[3 * r]] + sc[pl[3 * r + 1]]) + 0.0f;   // +0.0f folds -0 into +0
+                const uint32_t u = __float_as_uint(e);
+                const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending float order
+                hi = ~ord;                                                            // descending
+            }
+            k = ((uint64_t)hi << 32) | (uint32_t)r;
+        }
+        keys[r] = k;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < P / 2; t += 1024) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t a = keys[lo], c = keys[hi];
+                if ((a > c) == up) { keys[lo] = c; keys[hi] = a; }
+            }
+            __syncthreads();
+        }
+    }
+    int32_t *out = w.pivots + (int64_t)b * w.piv_stride * 3;
+    for (int p = threadIdx.x; p < w.k1; p += 1024) {
+        if (p < K) {
+            const int r = (int)(uint32_t)keys[p];
+            out[3 * p] = pl[3 * r];
+            out[3 * p + 1] = pl[3 * r + 1];
+            out[3 * p + 2] = pl[3 * r + 2];
+        } else {
+            out[3 * p] = -1;
+            out[3 * p + 1] = -1;
+            out[3 * p + 2] = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- standalone forward
+
+__global__ void __launch_bounds__(256) k_mlp_forward(const uint16_t *feat, int64_t m, float *scores,
+                                                     const uint16_t *wbf16, const float *w32)
+{
+    __shared__ MlpLds L;
+    load_params(L, wbf16, w32);
+    __syncthreads();
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < m; n += (int64_t)gridDim.x * 256) {
+        float x[19];
+#pragma unroll
+        for (int k = 0; k < 19; ++k) x[k] = bf2f(feat[n * 19 + k]);
+        scores[n] = forward(L, x);
+    }
+}
+
+// ---------------------------------------------------------------- training
+
+// Scratch layout, feature-major so that consecutive samples are consecutive:
+//   A1[64][m], A2[64][m], D1[64][m], D2[64][m], DS[m], LS[m]
+struct Scratch {
+    float *a1, *a2, *d1, *d2, *ds, *ls;
+    int64_t m;
+};
+
+__device__ __forceinline__ Scratch scratch_view(float *base, int64_t m)
+{
+    Scratch s;
+    s.a1 = base;
+    s.a2 = base + 64 * m;
+    s.d1 = base + 128 * m;
+    s.d2 = base + 192 * m;
+    s.ds = base + 256 * m;
+    s.ls = base + 257 * m;
+    s.m = m;
+    return s;
+}
+
+// Per sample: forward (bfloat16 activations), BCE-with-logits loss and the
+// deltas of the backward pass. ds is already divided by m (mean loss).
+__global__ void __launch_bounds__(256) k_mlp_fwdbwd(const uint16_t *feat, const uint8_t *labels, int64_t m,
+                                                    float *scratch, const uint16_t *wbf16, const float *w32)
+{
+    __shared__ MlpLds L;
+    load_params(L, wbf16, w32);
+    __syncthreads();
+    const Scratch S = scratch_view(scratch, m);
+    const float inv_m = 1.0f / (float)m;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < m; n += (int64_t)gridDim.x * 256) {
+        float x[19];
+#pragma unroll
+        for (int k = 0; k < 19; ++k) x[k] = bf2f(feat[n * 19 + k]);
+        // forward; gelu'(z1) and gelu'(z2) are parked in the D1 / D2 slots
+        float a1[64];
+#pragma unroll
+        for (int o = 0; o < 64; ++o) {
+            float acc = L.p[kB1 + o];
+#pragma unroll
+            for (int k = 0; k < 19; ++k) acc = __builtin_fmaf(L.p[kW1 + 19 * o + k], x[k], acc);
+            a1[o] = bfround(gelu(acc));
+            S.d1[o * m + n] = gelu_grad(acc);
+        }
+        float s = L.p[kB3];
+#pragma unroll 2
+        for (int o = 0; o < 64; ++o) {
+            float acc = L.p[kB2 + o];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(L.p[kW2 + 64 * o + k], a1[k], acc);
+            const float a = bfround(gelu(acc));
+            S.a2[o * m + n] = a;
+            S.d2[o * m + n] = gelu_grad(acc);
+            s = __builtin_fmaf(L.p[kW3 + o], a, s);
+        }
+#pragma unroll
+        for (int o = 0; o < 64; ++o) S.a1[o * m + n] = a1[o];
+        // loss and backward
+        const float y = labels[n] ? 1.0f : 0.0f;
+        const float loss = fmaxf(s, 0.0f) - s * y + log1pf(expf(-fabsf(s)));
+        const float ds = (1.0f / (1.0f + expf(-s)) - y) * inv_m;
+        float d2[64];
+#pragma unroll
+        for (int o = 0; o < 64; ++o) {
+            d2[o] = ds * L.p[kW3 + o] * S.d2[o * m + n];
+            S.d2[o * m + n] = d2[o];
+        }
+#pragma unroll 2
+        for (int k = 0; k < 64; ++k) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int o = 0; o < 64; ++o) acc = __builtin_fmaf(L.p[kW2 + 64 * o + k], d2[o], acc);
+            S.d1[k * m + n] = acc * S.d1[k * m + n];
+        }
+        S.ds[n] = ds;
+        S.ls[n] = loss * inv_m;
+    }
+}
+
+constexpr int kTile = 256;   // samples per weight-gradient work item
+constexpr int kSub = 32;     // samples staged in LDS at a time
+
+// Partial sums over one tile of samples of every gradient (and the loss).
+// Thread t owns a 4 x 4 block of dW2, up to 5 entries of dW1 and one of the
+// vectors (db1, db2, dW3, db3, loss); samples are summed in index order.
+__global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t m, const float *scratch,
+                                                   float *partial)
+{
+    __shared__ float sa1[64][kSub], sa2[64][kSub], sd1[64][kSub], sd2[64][kSub], sx[19][kSub], sds[kSub], sls[kSub];
+    const Scratch S = scratch_view(const_cast<float *>(scratch), m);
+    const int t = threadIdx.x;
+    const int o2 = 4 * (t >> 4), k2 = 4 * (t & 15);
+    const int o1 = t >> 2, kg = t & 3;
+    const int64_t n0 = (int64_t)blockIdx.x * kTile;
+    float g2[4][4] = {}, g1[5] = {}, gv = 0.0f;
+    for (int sub = 0; sub < kTile; sub += kSub) {
+        for (int idx = t; idx < 64 * kSub; idx += 256) {
+            const int f = idx / kSub, c = idx % kSub;
+            const int64_t n = n0 + sub + c;
+            const bool ok = n < m;
+            sa1[f][c] = ok ? S.a1[f * m + n] : 0.0f;
+            sa2[f][c] = ok ? S.a2[f * m + n] : 0.0f;
+            sd1[f][c] = ok ? S.d1[f * m + n] : 0.0f;
+            sd2[f][c] = ok ? S.d2[f * m + n] : 0.0f;
+            if (f < 19) sx[f][c] = ok ? bf2f(feat[n * 19 + f]) : 0.0f;
+            if (f == 19) sds[c] = ok ? S.ds[n] : 0.0f;
+            if (f == 20) sls[c] = ok ? S.ls[n] : 0.0f;
+        }
+        __syncthreads();
+        for (int c = 0; c < kSub; ++c) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) g2[a][e] = __builtin_fmaf(sd2[o2 + a][c], sa1[k2 + e][c], g2[a][e]);
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if (kg + 4 * q < 19) g1[q] = __builtin_fmaf(sd1[o1][c], sx[kg + 4 * q][c], g1[q]);
+            if (t < 64) gv += sd1[t][c];
+            else if (t < 128) gv += sd2[t - 64][c];
+            else if (t < 192) gv = __builtin_fmaf(sds[c], sa2[t - 128][c], gv);
+            else if (t == 192) gv += sds[c];
+            else if (t == 193) gv += sls[c];
+        }
+        __syncthreads();
+    }
+    float *out = partial + (int64_t)blockIdx.x * kGradSlots;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[kW2 + 64 * (o2 + a) + k2 + e] = g2[a][e];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        if (kg + 4 * q < 19) out[kW1 + 19 * o1 + kg + 4 * q] = g1[q];
+    if (t < 64) out[kB1 + t] = gv;
+    else if (t < 128) out[kB2 + t - 64] = gv;
+    else if (t < 192) out[kW3 + t - 128] = gv;
+    else if (t == 192) out[kB3] = gv;
+    else if (t == 193) out[TR_MLP_NPARAM] = gv;
+}
+
+// Sum the tiles' partials in tile order (deterministic).
+__global__ void __launch_bounds__(256) k_mlp_reduce(const float *partial, int64_t tiles, float *grads, float *loss)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kGradSlots) return;
+    float acc = 0.0f;
+    for (int64_t t = 0; t < tiles; ++t) acc += partial[t * kGradSlots + p];
+    if (p < TR_MLP_NPARAM) grads[p] = acc;
+    else if (loss) *loss = acc;
+}
+
+__global__ void __launch_bounds__(256) k_adam(float *w, float *mo, float *ve, uint16_t *wbf16, const float *g,
+                                              float lr, float c1, float c2)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= TR_MLP_NPARAM) return;
+    const float gp = g[p];
+    const float m = 0.9f * mo[p] + 0.1f * gp;
+    const float v = 0.999f * ve[p] + 0.001f * gp * gp;
+    mo[p] = m;
+    ve[p] = v;
+    const float nw = w[p] - lr * (m / c1) / (sqrtf(v / c2) + 1e-8f);
+    w[p] = nw;
+    wbf16[p] = f2bf(nw);
+}
+
+__global__ void k_to_bf16(const float *w, uint16_t *wbf16, int n)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < n) wbf16[p] = f2bf(w[p]);
+}
+
+int grid_for(int64_t m)
+{
+    const int64_t g = (m + 255) / 256;
+    return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+
+hipError_t ensure_scratch(MlpState *s, int64_t m)
+{
+    if (s->scratch_m < m) {
+        if (s->scratch) hipFree(s->scratch);
+        s->scratch = nullptr;
+        s->scratch_m = 0;
+        hipError_t e = hipMalloc(&s->scratch, sizeof(float) * 258 * (size_t)m);
+        if (e != hipSuccess) return e;
+        s->scratch_m = m;
+    }
+    const int64_t tiles = (m + kTile - 1) / kTile;
+    if (s->partial_tiles < tiles) {
+        if (s->partial) hipFree(s->partial);
+        s->partial = nullptr;
+        s->partial_tiles = 0;
+        hipError_t e = hipMalloc(&s->partial, sizeof(float) * kGradSlots * (size_t)tiles);
+        if (e != hipSuccess) return e;
+        s->partial_tiles = tiles;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t mlp_create(MlpState *s)
+{
+    hipError_t e = hipMalloc(&s->w32, sizeof(float) * TR_MLP_NPARAM);
+    if (e == hipSuccess) e = hipMalloc(&s->m, sizeof(float) * TR_MLP_NPARAM);
+    if (e == hipSuccess) e = hipMalloc(&s->v, sizeof(float) * TR_MLP_NPARAM);
+    if (e == hipSuccess) e = hipMalloc(&s->wbf16, sizeof(uint16_t) * TR_MLP_NPARAM);
+    if (e == hipSuccess) e = hipMalloc(&s->grads, sizeof(float) * kGradSlots);
+    return e;
+}
+
+void mlp_release(MlpState *s)
+{
+    for (void *p : {(void *)s->w32, (void *)s->m, (void *)s->v, (void *)s->wbf16, (void *)s->grads,
+                    (void *)s->scratch, (void *)s->partial})
+        if (p) hipFree(p);
+    *s = MlpState();
+}
+
+hipError_t mlp_set(MlpState *s, const float *host)
+{
+    std::vector<float> zero(TR_MLP_NPARAM, 0.0f);
+    hipError_t e = hipMemcpy(s->w32, host, sizeof(float) * TR_MLP_NPARAM, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->m, zero.data(), sizeof(float) * TR_MLP_NPARAM, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->v, zero.data(), sizeof(float) * TR_MLP_NPARAM, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_to_bf16, dim3((TR_MLP_NPARAM + 255) / 256), dim3(256), 0, 0, s->w32, s->wbf16, TR_MLP_NPARAM);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    s->step = 0;
+    return e;
+}
+
+hipError_t mlp_get(MlpState *s, float *host)
+{
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    return hipMemcpy(host, s->w32, sizeof(float) * TR_MLP_NPARAM, hipMemcpyDeviceToHost);
+}
+
+hipError_t mlp_forward(MlpState *s, const uint16_t *feat, int64_t m, float *scores, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mlp_forward, dim3(grid_for(m)), dim3(256), 0, st, feat, m, scores, s->wbf16, s->w32);
+    return hipGetLastError();
+}
+
+hipError_t mlp_grads(MlpState *s, const uint16_t *feat, const uint8_t *labels, int64_t m, float *grads, float *loss,
+                     hipStream_t st)
+{
+    hipError_t e = ensure_scratch(s, m);
+    if (e != hipSuccess) return e;
+    const int64_t tiles = (m + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_mlp_fwdbwd, dim3(grid_for(m)), dim3(256), 0, st, feat, labels, m, s->scratch, s->wbf16,
+                       s->w32);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((unsigned)tiles), dim3(256), 0, st, feat, m, s->scratch, s->partial);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kGradSlots + 255) / 256), dim3(256), 0, st, s->partial, tiles, grads, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_train_step(MlpState *s, const uint16_t *feat, const uint8_t *labels, int64_t m, float lr, float *loss,
+                          hipStream_t st)
+{
+    hipError_t e = mlp_grads(s, feat, labels, m, s->grads, loss, st);
+    if (e != hipSuccess) return e;
+    s->step += 1;
+    const float c1 = 1.0f - powf(0.9f, (float)s->step), c2 = 1.0f - powf(0.999f, (float)s->step);
+    hipLaunchKernelGGL(k_adam, dim3((TR_MLP_NPARAM + 255) / 256), dim3(256), 0, st, s->w32, s->m, s->v, s->wbf16,
+                       s->grads, lr, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(const Work &w, uint16_t *packed, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_features, dim3(grid), dim3(256), 0, st, w, packed);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mlp_rows, dim3(grid), dim3(256), 0, st, w, mlp.wbf16, mlp.w32);
+    int P = 1;
+    while (P < w.pool) P <<= 1;
+    static bool lds_raised = false;
+    if (!lds_raised) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_reorder), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            TR_MAX_POOL * (int)sizeof(uint64_t));
+        lds_raised = true;
+    }
+    hipLaunchKernelGGL(k_reorder, dim3(B), dim3(1024), (size_t)P * sizeof(uint64_t), st, w);
+    return hipGetLastError();
+}
+
+}  // namespace tr

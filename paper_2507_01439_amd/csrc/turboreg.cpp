@@ -1,0 +1,555 @@
+// libturboreg host side: handle and workspace, the launch sequence of the
+// registration path, hipGraph capture for batches, and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+#include "mlp.h"
+
+using namespace tr;
+
+namespace {
+
+struct GraphKey {
+    const void *src, *dst, *offsets, *out, *masks;
+    void *stream;
+    int32_t B, max_n;
+    tr_params p;
+    bool operator<(const GraphKey &o) const
+    {
+        return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
+    }
+};
+
+}  // namespace
+
+struct tr_handle {
+    int device = 0;
+    int num_cus = 256;
+    int32_t max_n = 0, max_batch = 0, max_k1 = 0, max_k2 = 0;
+    int32_t npad_max = 0, pool_cap = 0, k1_cap = 0, h_cap = 0, nblk_stride = 0, pre_stride = 0;
+    // workspace
+    PairDesc *pairs = nullptr;
+    PairState *state = nullptr;
+    Plan *plan = nullptr;
+    int32_t *pre = nullptr;
+    uint8_t *C = nullptr;
+    uint16_t *G = nullptr;
+    int32_t *hist = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
+    uint64_t *cand = nullptr;
+    int32_t *pivots_plain = nullptr, *pivots = nullptr, *cliques = nullptr, *inl = nullptr;
+    float *poses = nullptr;
+    int32_t *rowstat = nullptr;
+    uint16_t *feat = nullptr;
+    float *scores = nullptr;
+    tr_result *scratch_out = nullptr;   // results of feature-only passes
+    // learned scorer
+    MlpState mlp;
+    bool has_scorer = false;
+    // last call, for inspection
+    Work last{};
+    int32_t last_B = 0;
+    hipStream_t last_stream = nullptr;
+    bool last_valid = false;
+    // profiling
+    hipEvent_t ev[TR_NUM_STAGES + 1] = {};
+    bool prof_valid = false;
+    // captured batches
+    std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+template <typename T>
+hipError_t alloc(tr_handle *h, T **p, size_t count)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    h->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return hipSuccess;
+}
+
+void release(tr_handle *h)
+{
+    for (auto &g : h->graphs) {
+        hipGraphExecDestroy(g.second.second);
+        hipGraphDestroy(g.second.first);
+    }
+    h->graphs.clear();
+    for (auto &e : h->ev)
+        if (e) hipEventDestroy(e);
+    mlp_release(&h->mlp);
+    for (void *p : h->allocs) hipFree(p);
+    h->allocs.clear();
+}
+
+int grid_cap(tr_handle *h, int64_t items, int per_cu)
+{
+    int64_t cap = (int64_t)h->num_cus * per_cu;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(items, cap));
+}
+
+Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params &p, tr_result *out,
+               uint8_t *masks, bool learned)
+{
+    Work w{};
+    w.src = src;
+    w.dst = dst;
+    w.pairs = h->pairs;
+    w.state = h->state;
+    w.plan = h->plan;
+    w.pre = h->pre;
+    w.pre_stride = h->pre_stride;
+    w.max_n = h->max_n;
+    w.k1 = p.k1;
+    w.k2 = p.k2;
+    w.pool = learned ? p.k1 * p.pool_factor : p.k1;
+    w.H = p.k1 * p.k2;
+    w.graph = p.graph;
+    w.tau = p.tau;
+    w.theta = p.inlier_thresh;
+    w.C = h->C;
+    w.G = h->G;
+    w.hist = h->hist;
+    w.rowcnt = h->rowcnt;
+    w.blkcnt = h->blkcnt;
+    w.nblk_stride = h->nblk_stride;
+    w.cand = h->cand;
+    w.pool_cap = h->pool_cap;
+    w.pivots_plain = h->pivots_plain;
+    if (learned) { w.pivots = h->pivots; w.piv_stride = h->k1_cap; }
+    else { w.pivots = h->pivots_plain; w.piv_stride = h->pool_cap; }
+    w.cliques = h->cliques;
+    w.poses = h->poses;
+    w.inl = h->inl;
+    w.h_cap = h->h_cap;
+    w.rowstat = h->rowstat;
+    w.feat = h->feat;
+    w.scores = h->scores;
+    w.out = out;
+    w.masks = masks;
+    w.learned = learned ? 1 : 0;
+    return w;
+}
+
+tr_status check_params(tr_handle *h, const tr_params *p)
+{
+    if (!p) return TR_ERR_INVALID_ARG;
+    if (!(p->tau >= 0.0f) || !std::isfinite(p->tau)) return TR_ERR_INVALID_ARG;
+    if (!(p->inlier_thresh >= 0.0f) || !std::isfinite(p->inlier_thresh)) return TR_ERR_INVALID_ARG;
+    if (p->k1 < 1 || p->k2 < 1 || p->k2 > TR_MAX_K2) return TR_ERR_INVALID_ARG;
+    if (p->graph != TR_GRAPH_O2 && p->graph != TR_GRAPH_SC2) return TR_ERR_INVALID_ARG;
+    if (p->pivot_mode != TR_PIVOTS_PLAIN && p->pivot_mode != TR_PIVOTS_LEARNED) return TR_ERR_INVALID_ARG;
+    if (p->k1 > h->max_k1 || p->k2 > h->max_k2) return TR_ERR_WORKSPACE;
+    if (p->pivot_mode == TR_PIVOTS_LEARNED) {
+        if (p->pool_factor < 1) return TR_ERR_INVALID_ARG;
+        if ((int64_t)p->pool_factor * p->k1 > h->pool_cap) return TR_ERR_WORKSPACE;
+        if (!h->has_scorer) return TR_ERR_NO_SCORER;
+    }
+    return TR_OK;
+}
+
+// The launch sequence for B pairs (offsets on the device) or one pair (n_single).
+// features_only stops after the learned features.
+tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n_single, int32_t B,
+                  int32_t max_n, bool profile, bool features_only, hipStream_t s)
+{
+    const int64_t npad = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
+    const int64_t nb64 = npad / kCompatTile, nb128 = npad / kSc2Tile;
+    const int64_t rows_items = (int64_t)B * ((max_n + kRowsPerItem - 1) / kRowsPerItem);
+    auto mark = [&](int stage) {
+        if (profile) hipEventRecord(h->ev[stage], s);
+    };
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (x != hipSuccess && e == hipSuccess) e = x;
+    };
+    mark(TR_STAGE_PLAN);
+    chk(launch_plan(w, offsets, n_single, B, max_n, h->pairs, h->state, h->plan, h->pre, s));
+    chk(launch_prep(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
+    mark(TR_STAGE_COMPAT);
+    chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 8), s));
+    mark(TR_STAGE_SC2);
+    chk(launch_sc2(w, grid_cap(h, (int64_t)B * nb128 * (nb128 + 1) / 2, 2), s));
+    if (features_only) return e == hipSuccess ? TR_OK : TR_ERR_HIP;
+    mark(TR_STAGE_PIVOTS);
+    chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
+    mark(TR_STAGE_LEARNED);
+    if (w.learned) {
+        const int g = grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8);
+        chk(launch_features(w, nullptr, g, s));
+        chk(launch_learned_order(w, h->mlp, B, g, s));
+    }
+    mark(TR_STAGE_CLIQUES);
+    chk(launch_cliques(w, B, s));
+    mark(TR_STAGE_KABSCH);
+    chk(launch_kabsch(w, B, s));
+    mark(TR_STAGE_SCORE);
+    const int64_t score_items = (int64_t)B * ((w.H + kScoreHyp - 1) / kScoreHyp) * ((max_n + kScorePts - 1) / kScorePts);
+    chk(launch_score(w, grid_cap(h, score_items, 8), s));
+    mark(TR_STAGE_SELECT);
+    chk(launch_select(w, B, s));
+    mark(TR_NUM_STAGES);
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "turboreg: launch failed: %s\n", hipGetErrorString(e));
+        return TR_ERR_HIP;
+    }
+    return TR_OK;
+}
+
+void remember(tr_handle *h, const Work &w, int32_t B, hipStream_t s, bool profile)
+{
+    h->last = w;
+    h->last_B = B;
+    h->last_stream = s;
+    h->last_valid = true;
+    h->prof_valid = profile;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tr_status_string(int32_t s)
+{
+    switch (s) {
+    case TR_OK: return "ok";
+    case TR_ERR_INVALID_ARG: return "invalid argument";
+    case TR_ERR_NONFINITE: return "non-finite input coordinates";
+    case TR_ERR_NO_HYPOTHESIS: return "no valid TurboClique";
+    case TR_ERR_WORKSPACE: return "request exceeds the handle's workspace";
+    case TR_ERR_HIP: return "HIP error";
+    case TR_WARN_SCORER_FALLBACK: return "learned scores not finite; plain pivots used";
+    case TR_ERR_NO_SCORER: return "no learned scorer loaded";
+    case TR_ERR_BAD_BLOB: return "bad scorer weights blob";
+    default: return "unknown status";
+    }
+}
+
+tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t max_k1, int32_t max_k2,
+                    int32_t device)
+{
+    if (!out) return TR_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (max_n < 3 || max_n > 32767 || max_batch < 1 || max_k1 < 1 || max_k2 < 1 || max_k2 > TR_MAX_K2 ||
+        max_k1 > TR_MAX_POOL)
+        return TR_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TR_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return TR_ERR_HIP;
+    tr_handle *h = new (std::nothrow) tr_handle();
+    if (!h) return TR_ERR_HIP;
+    h->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
+    h->max_n = max_n;
+    h->max_batch = max_batch;
+    h->max_k1 = max_k1;
+    h->max_k2 = max_k2;
+    h->npad_max = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
+    h->pool_cap = std::min(TR_MAX_POOL, 8 * max_k1);
+    h->k1_cap = max_k1;
+    h->h_cap = max_k1 * max_k2;
+    h->nblk_stride = (max_n + kRowsPerItem - 1) / kRowsPerItem;
+    h->pre_stride = max_batch + 1;
+    const size_t B = max_batch, nn = (size_t)h->npad_max * h->npad_max;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    A(alloc(h, &h->pairs, B));
+    A(alloc(h, &h->state, B));
+    A(alloc(h, &h->plan, 1));
+    A(alloc(h, &h->pre, (size_t)kNumPrefix * h->pre_stride));
+    A(alloc(h, &h->C, B * nn));
+    A(alloc(h, &h->G, B * nn));
+    A(alloc(h, &h->hist, B * max_n));
+    A(alloc(h, &h->rowcnt, B * max_n * 2));
+    A(alloc(h, &h->blkcnt, B * h->nblk_stride * 2));
+    A(alloc(h, &h->cand, B * h->pool_cap));
+    A(alloc(h, &h->pivots_plain, B * h->pool_cap * 3));
+    A(alloc(h, &h->pivots, B * h->k1_cap * 3));
+    A(alloc(h, &h->cliques, B * h->h_cap * 3));
+    A(alloc(h, &h->poses, B * h->h_cap * 12));
+    A(alloc(h, &h->inl, B * h->h_cap));
+    A(alloc(h, &h->rowstat, B * max_n * 20));
+    A(alloc(h, &h->feat, B * max_n * 19));
+    A(alloc(h, &h->scores, B * max_n));
+    A(alloc(h, &h->scratch_out, B));
+    for (auto &ev : h->ev) A(hipEventCreate(&ev));
+    if (e == hipSuccess) A(mlp_create(&h->mlp));
+    if (e != hipSuccess) {
+        std::fprintf(stderr, "turboreg: tr_create failed: %s\n", hipGetErrorString(e));
+        release(h);
+        delete h;
+        return TR_ERR_HIP;
+    }
+    *out = h;
+    return TR_OK;
+}
+
+tr_status tr_destroy(tr_handle *h)
+{
+    if (!h) return TR_ERR_INVALID_ARG;
+    hipSetDevice(h->device);
+    hipDeviceSynchronize();
+    release(h);
+    delete h;
+    return TR_OK;
+}
+
+tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t n, const tr_params *p,
+                      tr_result *out_dev, uint8_t *mask_dev, void *stream)
+{
+    if (!h || !src || !dst || !out_dev || n < 3) return TR_ERR_INVALID_ARG;
+    if (n > h->max_n) return TR_ERR_WORKSPACE;
+    tr_status st = check_params(h, p);
+    if (st != TR_OK) return st;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
+    const bool profile = (p->flags & TR_FLAG_PROFILE) != 0;
+    Work w = make_work(h, src, dst, *p, out_dev, mask_dev, learned);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = enqueue(h, w, nullptr, n, 1, n, profile, false, s);
+    if (st == TR_OK) remember(h, w, 1, s, profile);
+    return st;
+}
+
+tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, const int32_t *offsets_dev, int32_t B,
+                            int32_t max_n, const tr_params *p, tr_result *out_dev, uint8_t *masks_dev, void *stream)
+{
+    if (!h || !src || !dst || !offsets_dev || !out_dev || B < 1 || max_n < 3) return TR_ERR_INVALID_ARG;
+    if (B > h->max_batch || max_n > h->max_n) return TR_ERR_WORKSPACE;
+    tr_status st = check_params(h, p);
+    if (st != TR_OK) return st;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
+    const bool profile = (p->flags & TR_FLAG_PROFILE) != 0;
+    Work w = make_work(h, src, dst, *p, out_dev, masks_dev, learned);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (profile || s == nullptr) {
+        // events (and the legacy default stream) stay out of captured graphs: run eagerly
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, profile, false, s);
+        if (st == TR_OK) remember(h, w, B, s, profile);
+        return st;
+    }
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    key.src = src;
+    key.dst = dst;
+    key.offsets = offsets_dev;
+    key.out = out_dev;
+    key.masks = masks_dev;
+    key.stream = stream;
+    key.B = B;
+    key.max_n = max_n;
+    key.p = *p;
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_ERR_HIP;
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, false, false, s);
+        hipError_t ec = hipStreamEndCapture(s, &g);
+        if (st != TR_OK || ec != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return st != TR_OK ? st : TR_ERR_HIP;
+        }
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+            hipGraphDestroy(g);
+            return TR_ERR_HIP;
+        }
+        it = h->graphs.emplace(key, std::make_pair(g, ge)).first;
+    }
+    if (hipGraphLaunch(it->second.second, s) != hipSuccess) return TR_ERR_HIP;
+    remember(h, w, B, s, false);
+    return TR_OK;
+}
+
+tr_status tr_features_batch(tr_handle *h, const float *src, const float *dst, const int32_t *offsets_dev, int32_t B,
+                            int32_t max_n, const tr_params *p, uint16_t *feat_dev, void *stream)
+{
+    if (!h || !src || !dst || !offsets_dev || !feat_dev || !p || B < 1 || max_n < 3) return TR_ERR_INVALID_ARG;
+    if (B > h->max_batch || max_n > h->max_n) return TR_ERR_WORKSPACE;
+    if (!(p->tau >= 0.0f) || !std::isfinite(p->tau)) return TR_ERR_INVALID_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    tr_params q = *p;
+    q.k1 = 1;
+    q.k2 = 1;
+    q.pool_factor = 1;
+    Work w = make_work(h, src, dst, q, h->scratch_out, nullptr, true);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, false, true, s);
+    if (st != TR_OK) return st;
+    if (launch_features(w, feat_dev, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s) !=
+        hipSuccess)
+        return TR_ERR_HIP;
+    remember(h, w, B, s, false);
+    return TR_OK;
+}
+
+tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst, size_t bytes, size_t *needed)
+{
+    if (!h || !h->last_valid || pair < 0 || pair >= h->last_B) return TR_ERR_INVALID_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    if (hipStreamSynchronize(h->last_stream) != hipSuccess) return TR_ERR_HIP;
+    PairDesc d;
+    if (hipMemcpy(&d, h->pairs + pair, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return TR_ERR_HIP;
+    const Work &w = h->last;
+    const size_t n = d.n;
+    size_t need = 0;
+    const void *srcp = nullptr;
+    size_t pitch = 0, width = 0, rows = 0;
+    switch (tap) {
+    case TR_TAP_C:
+        need = n * n; srcp = h->C + d.c_off; pitch = d.npad; width = n; rows = n; break;
+    case TR_TAP_G:
+        need = n * n * 2; srcp = h->G + d.g_off; pitch = (size_t)d.npad * 2; width = n * 2; rows = n; break;
+    case TR_TAP_PIVOTS:
+        if (w.learned) { need = (size_t)w.k1 * 12; srcp = h->pivots + (size_t)pair * h->k1_cap * 3; }
+        else { need = (size_t)w.k1 * 12; srcp = h->pivots_plain + (size_t)pair * h->pool_cap * 3; }
+        break;
+    case TR_TAP_PLAIN_PIVOTS:
+        need = (size_t)w.pool * 12; srcp = h->pivots_plain + (size_t)pair * h->pool_cap * 3; break;
+    case TR_TAP_CLIQUES:
+        need = (size_t)w.H * 12; srcp = h->cliques + (size_t)pair * h->h_cap * 3; break;
+    case TR_TAP_POSES:
+        need = (size_t)w.H * 48; srcp = h->poses + (size_t)pair * h->h_cap * 12; break;
+    case TR_TAP_IN:
+        need = (size_t)w.H * 4; srcp = h->inl + (size_t)pair * h->h_cap; break;
+    case TR_TAP_FEATURES:
+        need = n * 19 * 2; srcp = h->feat + (size_t)pair * h->max_n * 19; break;
+    case TR_TAP_SCORES:
+        need = n * 4; srcp = h->scores + (size_t)pair * h->max_n; break;
+    default: return TR_ERR_INVALID_ARG;
+    }
+    if (needed) *needed = need;
+    if (!host_dst) return TR_OK;
+    if (bytes < need) return TR_ERR_INVALID_ARG;
+    hipError_t e;
+    if (rows) e = hipMemcpy2D(host_dst, width, srcp, pitch, width, rows, hipMemcpyDeviceToHost);
+    else e = hipMemcpy(host_dst, srcp, need, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? TR_OK : TR_ERR_HIP;
+}
+
+tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count)
+{
+    if (!h || !ms || count < 0 || count > TR_NUM_STAGES || !h->prof_valid) return TR_ERR_INVALID_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    if (hipEventSynchronize(h->ev[TR_NUM_STAGES]) != hipSuccess) return TR_ERR_HIP;
+    for (int k = 0; k < count; ++k) {
+        float t = 0;
+        if (hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]) != hipSuccess) return TR_ERR_HIP;
+        ms[k] = t;
+    }
+    return TR_OK;
+}
+
+// ---- learned scorer ----
+
+tr_status tr_scorer_set(tr_handle *h, const float *params_host)
+{
+    if (!h || !params_host) return TR_ERR_INVALID_ARG;
+    for (int k = 0; k < TR_MLP_NPARAM; ++k)
+        if (!std::isfinite(params_host[k])) return TR_ERR_INVALID_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    if (mlp_set(&h->mlp, params_host) != hipSuccess) return TR_ERR_HIP;
+    h->has_scorer = true;
+    return TR_OK;
+}
+
+tr_status tr_scorer_get(tr_handle *h, float *params_host)
+{
+    if (!h || !params_host) return TR_ERR_INVALID_ARG;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    return mlp_get(&h->mlp, params_host) == hipSuccess ? TR_OK : TR_ERR_HIP;
+}
+
+static uint64_t fnv1a(const void *p, size_t n)
+{
+    const uint8_t *b = static_cast<const uint8_t *>(p);
+    uint64_t x = 1469598103934665603ull;
+    for (size_t k = 0; k < n; ++k) { x ^= b[k]; x *= 1099511628211ull; }
+    return x;
+}
+
+static const char kMagic[8] = {'T', 'R', 'M', 'L', 'P', '0', '0', '1'};
+static const size_t kBlobBytes = 8 + TR_MLP_NPARAM * 4 + 8;
+
+tr_status tr_scorer_save(tr_handle *h, void *blob, size_t capacity, size_t *written)
+{
+    if (!h || !blob) return TR_ERR_INVALID_ARG;
+    if (written) *written = kBlobBytes;
+    if (capacity < kBlobBytes) return TR_ERR_INVALID_ARG;
+    std::vector<float> w(TR_MLP_NPARAM);
+    tr_status st = tr_scorer_get(h, w.data());
+    if (st != TR_OK) return st;
+    uint8_t *b = static_cast<uint8_t *>(blob);
+    std::memcpy(b, kMagic, 8);
+    std::memcpy(b + 8, w.data(), TR_MLP_NPARAM * 4);
+    const uint64_t c = fnv1a(b + 8, TR_MLP_NPARAM * 4);
+    std::memcpy(b + 8 + TR_MLP_NPARAM * 4, &c, 8);
+    return TR_OK;
+}
+
+tr_status tr_scorer_load(tr_handle *h, const void *blob, size_t bytes)
+{
+    if (!h || !blob) return TR_ERR_INVALID_ARG;
+    if (bytes != kBlobBytes) return TR_ERR_BAD_BLOB;
+    const uint8_t *b = static_cast<const uint8_t *>(blob);
+    if (std::memcmp(b, kMagic, 8) != 0) return TR_ERR_BAD_BLOB;
+    uint64_t c;
+    std::memcpy(&c, b + 8 + TR_MLP_NPARAM * 4, 8);
+    if (c != fnv1a(b + 8, TR_MLP_NPARAM * 4)) return TR_ERR_BAD_BLOB;
+    std::vector<float> w(TR_MLP_NPARAM);
+    std::memcpy(w.data(), b + 8, TR_MLP_NPARAM * 4);
+    tr_status st = tr_scorer_set(h, w.data());
+    return st == TR_ERR_INVALID_ARG ? TR_ERR_BAD_BLOB : st;
+}
+
+tr_status tr_mlp_forward(tr_handle *h, const uint16_t *feat_dev, int64_t m, float *scores_dev, void *stream)
+{
+    if (!h || !feat_dev || !scores_dev || m < 0) return TR_ERR_INVALID_ARG;
+    if (!h->has_scorer) return TR_ERR_NO_SCORER;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    return mlp_forward(&h->mlp, feat_dev, m, scores_dev, static_cast<hipStream_t>(stream)) == hipSuccess ? TR_OK
+                                                                                                          : TR_ERR_HIP;
+}
+
+tr_status tr_mlp_grads(tr_handle *h, const uint16_t *feat_dev, const uint8_t *labels_dev, int64_t m,
+                       float *grads_dev, float *loss_dev, void *stream)
+{
+    if (!h || !feat_dev || !labels_dev || !grads_dev || m < 1) return TR_ERR_INVALID_ARG;
+    if (!h->has_scorer) return TR_ERR_NO_SCORER;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    return mlp_grads(&h->mlp, feat_dev, labels_dev, m, grads_dev, loss_dev, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? TR_OK
+               : TR_ERR_HIP;
+}
+
+tr_status tr_train_step(tr_handle *h, const uint16_t *feat_dev, const uint8_t *labels_dev, int64_t m, float lr,
+                        float *loss_dev, void *stream)
+{
+    if (!h || !feat_dev || !labels_dev || m < 1 || !(lr >= 0.0f)) return TR_ERR_INVALID_ARG;
+    if (!h->has_scorer) return TR_ERR_NO_SCORER;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    return mlp_train_step(&h->mlp, feat_dev, labels_dev, m, lr, loss_dev, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess
+               ? TR_OK
+               : TR_ERR_HIP;
+}
+
+}  // extern "C"

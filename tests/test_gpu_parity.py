@@ -1,0 +1,175 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bit-exact on C, the O2Graph weights, pivots, cliques, inlier numbers, the
+selected hypothesis and the mask; float32 poses within 1e-4 rad / 1e-4 m of
+the float64 oracle fit for every well-conditioned clique.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_01439_amd import synth
+from paper_2507_01439_amd import turboreg as T
+from parity import check_taps, run_single, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def reg():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    r = T.Registrar(max_n=5000, max_batch=8, max_k1=2000, max_k2=8)
+    yield r
+    r.close()
+
+
+def indoor(n, ratio, seed, **kw):
+    cfg = synth.CONFIGS["indoor_n1000"].replace(n=n, inlier_ratio=ratio, **kw)
+    return synth.make_pair(cfg, seed)
+
+
+@pytest.mark.parametrize("n", [3, 4, 63, 64, 65, 127, 128, 129, 255, 300])
+def test_small_ragged_sizes(reg, n):
+    p = indoor(n, 0.5, 100 + n)
+    prm = T.make_params(0.1, 0.1, k1=min(50, n * (n - 1) // 2 + 3), k2=2)
+    say(f"small n={n}")
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label=f"n={n}")
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_indoor_n1000(reg, seed):
+    cfg = synth.CONFIGS["indoor_n1000"]
+    p = synth.make_pair(cfg, synth.pair_seed(0, seed))
+    prm = T.params_from_config(cfg)
+    say(f"indoor n=1000 seed={seed}")
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    d = check_taps(reg, p.src, p.dst, prm, r, mask, label=f"c0 seed {seed}")
+    say(d)
+    assert synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
+
+
+def test_indoor_n5000_full_size(reg):
+    cfg = synth.CONFIGS["indoor_n5000"]
+    p = synth.make_pair(cfg, synth.pair_seed(1, 0))
+    prm = T.params_from_config(cfg)
+    say("indoor n=5000")
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    d = check_taps(reg, p.src, p.dst, prm, r, mask, label="c1")
+    say(d)
+    assert synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
+
+
+@pytest.mark.parametrize("k2", [1, 3, 8])
+def test_k2_values(reg, k2):
+    p = indoor(400, 0.3, 7)
+    prm = T.make_params(0.1, 0.1, k1=120, k2=k2)
+    say(f"k2={k2}")
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label=f"k2={k2}")
+
+
+def test_undirected_sc2_graph(reg):
+    p = indoor(350, 0.3, 8)
+    prm = T.make_params(0.1, 0.1, k1=100, k2=3, graph=T.TR_GRAPH_SC2)
+    say("undirected graph")
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label="sc2 graph")
+
+
+def test_k1_exceeds_pairs(reg):
+    p = indoor(12, 0.6, 9)
+    prm = T.make_params(0.1, 0.1, k1=100, k2=2)
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label="k1 > pairs")
+    assert r.n_pivots == 66
+
+
+def test_heavy_ties_noiseless_clique(reg):
+    # every pair compatible, every weight N - 2: the tie rule decides every pivot
+    p = indoor(200, 1.0, 10, sigma=0.0)
+    prm = T.make_params(0.01, 0.01, k1=300, k2=2)
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label="ties")
+    assert r.best_inliers == 200
+
+
+def test_all_outliers_no_hypothesis(reg):
+    p = indoor(300, 0.0, 11)
+    prm = T.make_params(1e-4, 0.1, k1=50, k2=2)
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label="outliers")
+    assert r.status == T.TR_ERR_NO_HYPOTHESIS and r.best_hyp == -1
+    assert list(r.R) == [1, 0, 0, 0, 1, 0, 0, 0, 1] and list(r.t) == [0, 0, 0]
+
+
+def test_nonfinite_input(reg):
+    p = indoor(200, 0.5, 12)
+    X = p.src.copy()
+    X[5, 1] = np.nan
+    X[17, 0] = np.inf
+    prm = T.make_params(0.1, 0.1, k1=60, k2=2)
+    r, mask = run_single(reg, torch, X, p.dst, prm)
+    assert r.status == T.TR_ERR_NONFINITE
+    C = reg.debug(T.TR_TAP_C)
+    assert not C[5].any() and not C[:, 17].any()
+    check_taps(reg, X, p.dst, prm, r, mask, label="nonfinite")
+
+
+def test_threshold_boundary_pairs(reg):
+    # exact 3-4-5 lengths put delta == tau exactly on many pairs
+    X = np.array([[0, 0, 0], [3, 4, 0], [0, 4, 3], [4, 0, 3], [6, 8, 0]], np.float32)
+    Y = np.array([[0, 0, 0], [0, 0, 5.25], [5.25, 0, 0], [0, 5.25, 0], [0, 0, 10.0]], np.float32)
+    prm = T.make_params(0.25, 0.5, k1=10, k2=2)
+    r, mask = run_single(reg, torch, X, Y, prm)
+    d = check_taps(reg, X, Y, prm, r, mask, label="boundary")
+    assert d["b32"] >= 3 and r.n_boundary_pairs == d["b32"]
+
+
+def test_duplicate_points(reg):
+    p = indoor(150, 0.4, 13)
+    X, Y = p.src.copy(), p.dst.copy()
+    X[10:20] = X[0]
+    Y[10:20] = Y[0]
+    prm = T.make_params(0.1, 0.1, k1=80, k2=2)
+    r, mask = run_single(reg, torch, X, Y, prm)
+    check_taps(reg, X, Y, prm, r, mask, label="duplicates")
+
+
+def test_deterministic_repeat(reg):
+    p = indoor(900, 0.1, 14)
+    prm = T.make_params(0.1, 0.1, k1=400, k2=2)
+    r1, m1 = run_single(reg, torch, p.src, p.dst, prm)
+    a = [reg.debug(t) for t in (T.TR_TAP_G, T.TR_TAP_CLIQUES, T.TR_TAP_POSES, T.TR_TAP_IN)]
+    r2, m2 = run_single(reg, torch, p.src, p.dst, prm)
+    b = [reg.debug(t) for t in (T.TR_TAP_G, T.TR_TAP_CLIQUES, T.TR_TAP_POSES, T.TR_TAP_IN)]
+    assert bytes(r1) == bytes(r2) and np.array_equal(m1, m2)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_host_argument_errors(reg):
+    p = indoor(50, 0.5, 15)
+    src, dst = to_dev(torch, p.src), to_dev(torch, p.dst)
+    out = torch.empty(80, dtype=torch.uint8, device="cuda")
+    bad = [
+        (2, T.make_params(0.1, 0.1, 10, 2), T.TR_ERR_INVALID_ARG),
+        (50, T.make_params(0.1, 0.1, 0, 2), T.TR_ERR_INVALID_ARG),
+        (50, T.make_params(0.1, 0.1, 10, 9), T.TR_ERR_INVALID_ARG),
+        (50, T.make_params(float("nan"), 0.1, 10, 2), T.TR_ERR_INVALID_ARG),
+        (50, T.make_params(0.1, 0.1, 10, 2, graph=5), T.TR_ERR_INVALID_ARG),
+        (50, T.make_params(0.1, 0.1, 5000, 2), T.TR_ERR_WORKSPACE),
+        (6000, T.make_params(0.1, 0.1, 10, 2), T.TR_ERR_WORKSPACE),
+        (50, T.make_params(0.1, 0.1, 10, 2, pivot_mode=T.TR_PIVOTS_LEARNED), None),
+    ]
+    for n, prm, want in bad:
+        rc = T.lib().tr_register(reg.h, T._ptr(src), T._ptr(dst), n, T.ct.byref(prm), T._ptr(out), None, T._stream())
+        if want is None:
+            assert rc in (T.TR_ERR_NO_SCORER, T.TR_OK)
+        else:
+            assert rc == want, (n, rc)
+    rc = T.lib().tr_register(reg.h, None, T._ptr(dst), 50, T.ct.byref(T.make_params(0.1, 0.1, 10, 2)),
+                             T._ptr(out), None, T._stream())
+    assert rc == T.TR_ERR_INVALID_ARG
