@@ -161,8 +161,11 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
 enum { TR_STAGE_PLAN = 0, TR_STAGE_COMPAT, TR_STAGE_SC2, TR_STAGE_PIVOTS, TR_STAGE_LEARNED,
        TR_STAGE_CLIQUES, TR_STAGE_KABSCH, TR_STAGE_SCORE, TR_STAGE_SELECT, TR_NUM_STAGES };
 
-/* Milliseconds each stage took in the last call made with TR_FLAG_PROFILE
- * (HIP events on the call's stream; synchronises it). count <= TR_NUM_STAGES. */
+/* Average milliseconds per stage over the calls made with TR_FLAG_PROFILE
+ * since the previous read (HIP events recorded on each call's stream, kept in
+ * a ring so profiled calls never wait on the host). Synchronises those events
+ * and resets the averages. TR_ERR_INVALID_ARG if no profiled call was made.
+ * count <= TR_NUM_STAGES. */
 tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count);
 
 const char *tr_status_string(int32_t status);

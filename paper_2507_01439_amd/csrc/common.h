@@ -7,10 +7,12 @@
 
 namespace tr {
 
-constexpr int kSc2Tile = 128;     // output tile edge of the int8 MFMA SC2 kernel; npad is a multiple
+constexpr int kSc2Tile = 256;     // output tile edge of the int8 MFMA SC2 kernel; npad is a multiple
+constexpr int kHistGroups = 16;   // SC2 tiles add their weight histograms into this many copies per pair
 constexpr int kCompatTile = 64;   // tile edge of the compatibility kernel
 constexpr int kRowsPerItem = 16;  // rows per work item of the pivot scans
-constexpr int kPrepRows = 256;    // rows per work item of the prep kernel
+constexpr int kPrepRows = 256;    // rows per work item of the prep / feature kernels
+constexpr int kRankSortMax = 4096; // candidate lists up to this size are ordered by a rank sort
 constexpr int kScoreHyp = 256;    // hypotheses per scoring work item (one per thread)
 constexpr int kScorePts = 128;    // points per scoring work item
 
@@ -59,7 +61,9 @@ struct Work {
     float tau, theta;
     uint8_t *C;               // C arena
     uint16_t *G;              // G arena
-    int32_t *hist;            // max_batch x max_n weight histogram
+    int32_t *ghist;           // max_batch x kHistGroups x max_n weight histograms (filled by the SC2 epilogue)
+    int32_t *rowmax;          // max_batch x max_n: max_{j>i} G_ij (filled by the SC2 epilogue)
+    int32_t *cnt_part;        // per compatibility work item: (boundary pairs, edges)
     int32_t *rowcnt;          // max_batch x max_n x 2 (count > alpha, count == alpha)
     int32_t *blkcnt;          // max_batch x nblk x 2
     int32_t nblk_stride;      // blocks of kRowsPerItem rows per pair (for max_n)
@@ -91,14 +95,47 @@ __device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)
     return lo;
 }
 
+// Ascending bitonic sort of P keys in LDS by one workgroup (P a power of two,
+// P >= 64). Stages with stride >= 64 exchange through LDS; the stages with
+// stride < 64 of each merge run on 64-key blocks held one key per lane and
+// exchanged with wave shuffles, so a merge costs one barrier per LDS stage
+// plus one.
+__device__ inline void bitonic_sort_lds(uint64_t *keys, int P)
+{
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nthr >> 6;
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride >= 64; stride >>= 1) {
+            for (int t = tid; t < P / 2; t += nthr) {
+                const int lo = 2 * t - (t & (stride - 1)), hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t a = keys[lo], c = keys[hi];
+                if ((a > c) == up) { keys[lo] = c; keys[hi] = a; }
+            }
+            __syncthreads();
+        }
+        for (int blk = wv; blk < P / 64; blk += nw) {
+            const int p = blk * 64 + lane;
+            const bool up = (p & size) == 0;
+            uint64_t key = keys[p];
+            for (int stride = (size >> 1) < 32 ? (size >> 1) : 32; stride >= 1; stride >>= 1) {
+                const uint64_t other = __shfl_xor(key, stride, 64);
+                const bool keep_min = ((lane & stride) == 0) == up;
+                key = keep_min ? (key < other ? key : other) : (key > other ? key : other);
+            }
+            keys[p] = key;
+        }
+        __syncthreads();
+    }
+}
+
 // ---- launchers (one per kernel family); each returns the launch's hipError_t ----
 hipError_t launch_plan(const Work &w, const int32_t *offsets, int32_t n_single, int32_t B,
                        int32_t max_n, PairDesc *pairs, PairState *state, Plan *plan, int32_t *pre,
                        hipStream_t s);
-hipError_t launch_prep(const Work &w, int grid, hipStream_t s);
 hipError_t launch_compat(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
+hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
 hipError_t launch_cliques(const Work &w, int B, hipStream_t s);
 hipError_t launch_kabsch(const Work &w, int B, hipStream_t s);
 hipError_t launch_score(const Work &w, int grid, hipStream_t s);

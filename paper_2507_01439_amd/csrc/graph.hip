@@ -6,30 +6,6 @@
 namespace tr {
 namespace {
 
-template <typename T>
-__device__ T block_exclusive_scan(T v, T *lds, T &total)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    T x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) lds[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        T acc = 0;
-        for (int k = 0; k < nw; ++k) { T t = lds[k]; lds[k] = acc; acc += t; }
-        lds[nw] = acc;
-    }
-    __syncthreads();
-    T res = lds[wid] + x - v;
-    total = lds[nw];
-    __syncthreads();
-    return res;
-}
-
 __device__ __forceinline__ int wave_sum(int v)
 {
 #pragma unroll
@@ -50,15 +26,85 @@ __device__ __forceinline__ void tri_decode(int t, int nb, int &bi, int &bj)
     bj = r + (t - r * (2 * nb - r + 1) / 2);
 }
 
+// SC2 tile order: the upper triangle of nb x nb tiles is walked in super-tiles
+// of kSuper x kSuper (super-rows I <= J, row-major), tiles row-major inside.
+// Consecutive items then share few row blocks of C, so the tiles one XCD runs
+// at the same time reuse each other's operand rows in its L2.
+constexpr int kSuper = 5;
+
+__device__ __forceinline__ void super_decode(int t, int nb, int &bi, int &bj)
+{
+    const int ns = (nb + kSuper - 1) / kSuper;
+    for (int I = 0; I < ns; ++I) {
+        const int r0 = I * kSuper, r1 = min(nb, r0 + kSuper);
+        for (int J = I; J < ns; ++J) {
+            const int c0 = J * kSuper, c1 = min(nb, c0 + kSuper);
+            int cnt;
+            if (I == J) { const int s = r1 - r0; cnt = s * (s + 1) / 2; }
+            else cnt = (r1 - r0) * (c1 - c0);
+            if (t < cnt) {
+                if (I == J) {
+                    // triangle of side s: row r holds s - r tiles
+                    int r = 0, s = r1 - r0;
+                    while (t >= s - r) { t -= s - r; ++r; }
+                    bi = r0 + r;
+                    bj = bi + t;
+                } else {
+                    bi = r0 + t / (c1 - c0);
+                    bj = c0 + t % (c1 - c0);
+                }
+                return;
+            }
+            t -= cnt;
+        }
+    }
+    bi = bj = 0;   // not reached for t < nb (nb + 1) / 2
+}
+
 // ---------------------------------------------------------------- planning
 
+// Exclusive scan of NV values per thread across the workgroup (one pass).
+template <int NV>
+__device__ void block_scan_multi(const int64_t (&v)[NV], int64_t (&excl)[NV], int64_t (&total)[NV],
+                                 int64_t (*lds)[NV])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int64_t x[NV];
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+        x[s] = v[s];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t y = __shfl_up(x[s], o, 64);
+            if (lane >= o) x[s] += y;
+        }
+        if (lane == 63) lds[wid][s] = x[s];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        int64_t acc = 0;
+        for (int k = 0; k < nw; ++k) { const int64_t t = lds[k][threadIdx.x]; lds[k][threadIdx.x] = acc; acc += t; }
+        lds[nw][threadIdx.x] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NV; ++s) {
+        excl[s] = lds[wid][s] + x[s] - v[s];
+        total[s] = lds[nw][s];
+    }
+    __syncthreads();
+}
+
+// One workgroup: per-pair sizes, work-item counts and their prefix sums, arena
+// offsets, and zeroed per-pair state.
 __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n_single, int32_t B,
                                                int32_t max_n, int32_t pool, int32_t H,
                                                PairDesc *pairs, PairState *state, Plan *plan,
                                                int32_t *pre, int32_t pre_stride)
 {
-    __shared__ int64_t lds[17];
-    int64_t carry[kNumPrefix + 1] = {0, 0, 0, 0, 0, 0};
+    constexpr int NV = kNumPrefix + 1;   // the work-list stages, then the arena bytes
+    __shared__ int64_t lds[17][NV];
+    int64_t carry[NV] = {};
     for (int base = 0; base < B; base += blockDim.x) {
         const int b = base + threadIdx.x;
         int32_t n = 0, pt = 0;
@@ -70,35 +116,32 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
         }
         const int32_t nn = ok ? n : 0;
         const int32_t npad = ok ? (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile : 0;
-        const int64_t nb64 = npad / kCompatTile, nb128 = npad / kSc2Tile;
-        int64_t cnt[kNumPrefix + 1];
+        const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
+        int64_t cnt[NV], excl[NV], tot[NV];
         cnt[kPrep] = (nn + kPrepRows - 1) / kPrepRows;
         cnt[kCompat] = nb64 * (nb64 + 1) / 2;
-        cnt[kSc2] = nb128 * (nb128 + 1) / 2;
+        cnt[kSc2] = nbs * (nbs + 1) / 2;
         cnt[kRowBlk] = (nn + kRowsPerItem - 1) / kRowsPerItem;
         cnt[kScore] = ok ? (int64_t)((H + kScoreHyp - 1) / kScoreHyp) * ((nn + kScorePts - 1) / kScorePts) : 0;
         cnt[kNumPrefix] = (int64_t)npad * npad;   // arena bytes
-        int64_t excl[kNumPrefix + 1];
-        for (int s = 0; s <= kNumPrefix; ++s) {
-            int64_t tot;
-            excl[s] = block_exclusive_scan<int64_t>(cnt[s], lds, tot) + carry[s];
-            carry[s] += tot;
-        }
+        block_scan_multi<NV>(cnt, excl, tot, lds);
         if (b < B) {
-            for (int s = 0; s < kNumPrefix; ++s) pre[s * pre_stride + b] = (int32_t)excl[s];
+            for (int s = 0; s < kNumPrefix; ++s) pre[s * pre_stride + b] = (int32_t)(excl[s] + carry[s]);
             PairDesc d;
             d.n = nn;
             d.npad = npad;
             d.pt_off = pt;
             const int64_t pairs_all = (int64_t)nn * (nn - 1) / 2;
             d.kpiv = (int32_t)(pairs_all < pool ? pairs_all : pool);
-            d.c_off = excl[kNumPrefix];
-            d.g_off = excl[kNumPrefix];
+            d.c_off = excl[kNumPrefix] + carry[kNumPrefix];
+            d.g_off = d.c_off;
             pairs[b] = d;
             PairState st = {};
-            st.status = (b < B && !ok) ? TR_ERR_INVALID_ARG : TR_OK;
+            st.status = ok ? TR_OK : TR_ERR_INVALID_ARG;
             state[b] = st;
         }
+#pragma unroll
+        for (int s = 0; s < NV; ++s) carry[s] += tot[s];
     }
     if (threadIdx.x == 0) {
         plan->B = B;
@@ -109,26 +152,18 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
     }
 }
 
-// Zero the per-row accumulators of every pair and flag non-finite input.
-__global__ void __launch_bounds__(256) k_prep(Work w)
+// Learned mode: zero the per-row feature accumulators.
+__global__ void __launch_bounds__(256) k_prep_learned(Work w)
 {
     const int total = w.plan->total[kPrep], B = w.plan->B;
     const int32_t *pre = w.pre + kPrep * w.pre_stride;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
         const int i = (item - pre[b]) * kPrepRows + threadIdx.x;
-        bool bad = false;
-        if (i < d.n) {
-            w.hist[(int64_t)b * w.max_n + i] = 0;
-            if (w.learned) {
-                int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
-                for (int f = 0; f < 20; ++f) rs[f] = 0;
-            }
-            const float *x = w.src + 3 * (int64_t)(d.pt_off + i), *y = w.dst + 3 * (int64_t)(d.pt_off + i);
-            for (int k = 0; k < 3; ++k) bad |= !isfinite(x[k]) || !isfinite(y[k]);
+        if (i < w.pairs[b].n) {
+            int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+            for (int f = 0; f < 20; ++f) rs[f] = 0;
         }
-        if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&w.state[b].nonfinite, 1);
     }
 }
 
@@ -145,37 +180,55 @@ __device__ __forceinline__ float length32(float ax, float ay, float az)
     return __builtin_sqrtf(s);
 }
 
-// One 64 x 64 tile (bi <= bj) of C per work item: each thread evaluates a
-// 4 x 4 block of pairs once and writes it to both triangles with 4-byte
-// stores (16 lanes cover one 64-byte row segment).
+constexpr int kTileStride = 80;   // LDS byte-tile row stride (16-byte aligned rows)
+
+// One 64 x 64 tile (bi <= bj) of C per work item. Each thread evaluates a
+// 4 x 4 block of pairs once; the tile and its transpose are staged in LDS and
+// written to both triangles with 16-byte stores, four lanes per 64-byte row
+// segment. Per-tile counts (boundary pairs, edges) go to a per-item slot, so
+// no atomics are needed; non-finite inputs are flagged by the diagonal tiles.
 __global__ void __launch_bounds__(256) k_compat(Work w)
 {
     __shared__ float px[2][64][3], py[2][64][3];
+    __shared__ __attribute__((aligned(16))) uint8_t tile[2][64 * kTileStride];
     __shared__ int32_t hrow[64][17], hcol[64][17];   // learned mode: delta histogram and degree per row / col
+    __shared__ int32_t red[4][2];
     const int total = w.plan->total[kCompat], B = w.plan->B;
     const int32_t *pre = w.pre + kCompat * w.pre_stride;
-    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63, wv = tid >> 6;
     const float tau = w.tau, q = tau * 0.25f;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int b = find_pair(pre, B, item);
         const PairDesc d = w.pairs[b];
         int bi, bj;
         tri_decode(item - pre[b], d.npad / kCompatTile, bi, bj);
+        const bool diag = bi == bj;
+        bool bad = false;
         if (tid < 128) {
             const int side = tid >> 6, r = tid & 63;
             const int i = (side ? bj : bi) * kCompatTile + r;
             for (int k = 0; k < 3; ++k) {
-                px[side][r][k] = i < d.n ? w.src[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
-                py[side][r][k] = i < d.n ? w.dst[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
+                const float xv = i < d.n ? w.src[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
+                const float yv = i < d.n ? w.dst[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
+                px[side][r][k] = xv;
+                py[side][r][k] = yv;
+                bad |= diag && side == 0 && !(isfinite(xv) && isfinite(yv));
             }
+        }
+        if (diag) {   // the diagonal tiles clear this pair's histogram copies and row maxima for their 64 rows
+            for (int k = tid; k < kHistGroups * 64; k += 256) {
+                const int i = bi * kCompatTile + (k & 63);
+                if (i < d.n) w.ghist[((int64_t)b * kHistGroups + (k >> 6)) * w.max_n + i] = 0;
+            }
+            if (tid < 64 && bi * kCompatTile + tid < d.n) w.rowmax[(int64_t)b * w.max_n + bi * kCompatTile + tid] = 0;
         }
         if (w.learned) {
             for (int k = tid; k < 64 * 17; k += 256) { hrow[k / 17][k % 17] = 0; hcol[k / 17][k % 17] = 0; }
         }
+        if (__any(bad) && lane == 0) atomicOr(&w.state[b].nonfinite, 1);
         __syncthreads();
         uint32_t rowbits[4] = {0, 0, 0, 0}, colbits[4] = {0, 0, 0, 0};
         int nbnd = 0, nedge = 0;
-        const bool diag = bi == bj;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int r = ty * 4 + a, i = bi * kCompatTile + r;
@@ -208,34 +261,32 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
                 }
             }
         }
-        uint8_t *Cb = w.C + d.c_off;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int64_t i = bi * kCompatTile + ty * 4 + a;
-            *reinterpret_cast<uint32_t *>(Cb + i * d.npad + bj * kCompatTile + tx * 4) = rowbits[a];
-        }
-        if (!diag) {
+        for (int a = 0; a < 4; ++a)
+            *reinterpret_cast<uint32_t *>(&tile[0][(ty * 4 + a) * kTileStride + tx * 4]) = rowbits[a];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t j = bj * kCompatTile + tx * 4 + e;
-                *reinterpret_cast<uint32_t *>(Cb + j * d.npad + bi * kCompatTile + ty * 4) = colbits[e];
-            }
-        }
+        for (int e = 0; e < 4; ++e)
+            *reinterpret_cast<uint32_t *>(&tile[1][(tx * 4 + e) * kTileStride + ty * 4]) = colbits[e];
         nbnd = wave_sum(nbnd);
         nedge = wave_sum(nedge);
-        if ((tid & 63) == 0 && (nbnd | nedge)) {
-            atomicAdd(&w.state[b].n_boundary, nbnd);
-            atomicAdd(&w.state[b].n_edges, nedge);
-        }
+        if (lane == 0) { red[wv][0] = nbnd; red[wv][1] = nedge; }
+        __syncthreads();
+        uint8_t *Cb = w.C + d.c_off;
+        const int r = tid >> 2, c16 = (tid & 3) * 16;
+        *reinterpret_cast<uint4 *>(Cb + ((int64_t)bi * kCompatTile + r) * d.npad + bj * kCompatTile + c16) =
+            *reinterpret_cast<const uint4 *>(&tile[0][r * kTileStride + c16]);
+        if (!diag)
+            *reinterpret_cast<uint4 *>(Cb + ((int64_t)bj * kCompatTile + r) * d.npad + bi * kCompatTile + c16) =
+                *reinterpret_cast<const uint4 *>(&tile[1][r * kTileStride + c16]);
+        if (tid < 2) w.cnt_part[2 * (int64_t)item + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
         if (w.learned) {
-            __syncthreads();
             for (int k = tid; k < 64 * 17; k += 256) {
-                const int r = k / 17, f = k % 17;
+                const int rr = k / 17, f = k % 17;
                 // feature slots: 0 degree, 3..18 histogram
                 const int slot = f == 16 ? 0 : 3 + f;
-                const int i = bi * kCompatTile + r, j = bj * kCompatTile + r;
-                if (i < d.n && hrow[r][f]) atomicAdd(&w.rowstat[((int64_t)b * w.max_n + i) * 20 + slot], hrow[r][f]);
-                if (!diag && j < d.n && hcol[r][f]) atomicAdd(&w.rowstat[((int64_t)b * w.max_n + j) * 20 + slot], hcol[r][f]);
+                const int i = bi * kCompatTile + rr, j = bj * kCompatTile + rr;
+                if (i < d.n && hrow[rr][f]) atomicAdd(&w.rowstat[((int64_t)b * w.max_n + i) * 20 + slot], hrow[rr][f]);
+                if (!diag && j < d.n && hcol[rr][f]) atomicAdd(&w.rowstat[((int64_t)b * w.max_n + j) * 20 + slot], hcol[rr][f]);
             }
         }
         __syncthreads();
@@ -246,108 +297,222 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(1))) void gvoid;
+typedef __attribute__((address_space(3))) void lvoid;
 
-constexpr int kKT = 128;          // K bytes per pipeline stage
-constexpr int kLdsStride = 144;   // padded LDS row stride: 16 lanes of a ds_read_b128 hit distinct banks
-constexpr int kLdsMat = kSc2Tile * kLdsStride;
+constexpr int kBK = 64;                        // K bytes per pipeline stage
+constexpr int kStages = 4;                     // LDS ring depth (three stages in flight)
+constexpr int kMatBytes = kSc2Tile * kBK;      // one operand's stage: 256 rows x 64 bytes
+constexpr int kStageBytes = 2 * kMatBytes;
+constexpr int kRingBytes = kStages * kStageBytes;   // 128 KiB; also holds the finished tile as uint16
+constexpr int kHistLdsBins = 8192;             // weights below this are histogrammed in LDS first
+constexpr int kSc2Lds = kRingBytes + kHistLdsBins * 4;   // 160 KiB
 
-// G[i][j] = C_ij * sum_k C_ik C_jk for i < j < n, over 128 x 128 output tiles
+// Wait until at most N vector-memory loads of this wave are outstanding, then
+// meet the other waves. The memory clobber keeps LDS reads of the new stage
+// after it; unlike __syncthreads it does not drain the later stages in flight.
+#define SC2_WAIT_BARRIER(N) asm volatile("s_waitcnt vmcnt(" #N ")\n\ts_barrier" ::: "memory")
+
+// G[i][j] = C_ij * sum_k C_ik C_jk for i < j < n over 256 x 256 output tiles
 // with bi <= bj. C is symmetric, so the product is C C^T and both MFMA
-// operands are rows of C read along k. 4 waves in a 2 x 2 layout each own a
-// 64 x 64 sub-tile as 2 x 2 blocks of v_mfma_i32_32x32x32_i8 (int32 sums are
-// exact: at most N - 2). Global -> LDS staging is double-buffered; work items
-// are split into 8 contiguous ranges, one per XCD, so that tiles sharing rows
-// of C share an L2.
-__global__ void __launch_bounds__(256, 2) k_sc2(Work w)
+// operands are rows of C read along k.
+//
+// Four waves in a 2 x 2 layout each own a 128 x 128 sub-tile as 4 x 4 blocks
+// of v_mfma_i32_32x32x32_i8 (int32 sums are exact: at most N - 2; the
+// accumulators live in AGPRs). Operand stages of 64 bytes of k arrive by
+// direct global->LDS 16-byte loads into a four-deep ring, three stages in
+// flight; a row's four 16-byte chunks are stored XOR-swizzled by (row/4) mod 4
+// so the fragment reads (ds_read_b128) are free of bank conflicts. Work items
+// are split into 8 contiguous ranges, one per XCD, so tiles that share rows of
+// C share an L2.
+//
+// Epilogue: the tile is restaged in LDS as uint16 (weights are below 2^16),
+// then read row-major: masked by C_ij and i < j < n, stored with 16-byte
+// writes, counted into a weight histogram (LDS, added into one of
+// kHistGroups copies per pair) and reduced into the per-row maximum of the
+// upper triangle. In learned mode it also adds row and column sums / maxima
+// of the symmetric SC2 matrix for the per-match features.
+__global__ void __launch_bounds__(256, 1) k_sc2(Work w)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kLdsMat];
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    int32_t *hist = reinterpret_cast<int32_t *>(smem + kRingBytes);
+    uint16_t *T = reinterpret_cast<uint16_t *>(smem);
     const int total = w.plan->total[kSc2], B = w.plan->B;
     const int32_t *pre = w.pre + kSc2 * w.pre_stride;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
     const int xcd = blockIdx.x & 7, nx = (gridDim.x - xcd + 7) >> 3, lb = blockIdx.x >> 3;
     const int chunk = (total + 7) >> 3;
     const int end = min(total, (xcd + 1) * chunk);
+    // fragment read offsets inside a stage: row (lane & 31) of a 32-row block, chunk (ks*2 + lane/32)
+    const int frow = lane & 31, fsw = (frow >> 2) & 3;
+    const int foff0 = frow * kBK + 16 * ((lane >> 5) ^ fsw), foff1 = frow * kBK + 16 * ((2 + (lane >> 5)) ^ fsw);
+    for (int k = tid; k < kHistLdsBins; k += 256) hist[k] = 0;
+    __syncthreads();
     for (int item = xcd * chunk + lb; item < end; item += nx) {
         const int b = find_pair(pre, B, item);
         const PairDesc d = w.pairs[b];
         int bi, bj;
-        tri_decode(item - pre[b], d.npad / kSc2Tile, bi, bj);
+        super_decode(item - pre[b], d.npad / kSc2Tile, bi, bj);
         const uint8_t *Cb = w.C + d.c_off;
         const int64_t npad = d.npad;
-        const int nk = d.npad / kKT;
-        // global load slots: 8 x 16 B per thread, A rows then B rows, 8 lanes per 128-byte row
-        const uint8_t *gsrc[8];
-        int ldsoff[8];
+        const int nk = d.npad / kBK;
+        // load s of a stage: row r = (s&3)*64 + wv*16 + lane/4 of operand s/4 into LDS chunk lane&3,
+        // which holds the row's global chunk (lane&3) ^ ((r/4)&3)
+        uint32_t goff[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int idx = q * 256 + tid, mat = idx >> 10, r = (idx >> 3) & 127, ch = idx & 7;
-            const int64_t row = (int64_t)(mat ? bj : bi) * kSc2Tile + r;
-            gsrc[q] = Cb + row * npad + ch * 16;
-            ldsoff[q] = mat * kLdsMat + r * kLdsStride + ch * 16;
+        for (int s = 0; s < 8; ++s) {
+            const int r = (s & 3) * 64 + wv * 16 + (lane >> 2);
+            const int64_t row = (int64_t)((s >> 2) ? bj : bi) * kSc2Tile + r;
+            goff[s] = (uint32_t)(row * npad + 16 * ((lane & 3) ^ ((r >> 2) & 3)));
         }
-        v4i stage[8];
+        auto issue = [&](int kt) {
+            uint8_t *dst = smem + (kt % kStages) * kStageBytes + wv * 1024;
+            const uint8_t *src = Cb + (int64_t)kt * kBK;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) stage[q] = *reinterpret_cast<const v4i *>(gsrc[q]);
+            for (int s = 0; s < 8; ++s)
+                __builtin_amdgcn_global_load_lds((gvoid *)(src + goff[s]),
+                                                 (lvoid *)(dst + (s >> 2) * kMatBytes + (s & 3) * 4096), 16, 0, 0);
+        };
+        v16i acc[4][4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) *reinterpret_cast<v4i *>(&lds[0][0][0] + ldsoff[q]) = stage[q];
-        __syncthreads();
-        v16i acc[2][2];
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+            for (int y = 0; y < 4; ++y) acc[x][y] = (v16i){};
 #pragma unroll
-            for (int y = 0; y < 2; ++y) acc[x][y] = (v16i){};
-        const int arow = wm * 64 + (lane & 31), brow = wn * 64 + (lane & 31), koff = (lane >> 5) * 16;
+        for (int kt = 0; kt < kStages - 1; ++kt)
+            if (kt < nk) issue(kt);
         for (int kt = 0; kt < nk; ++kt) {
-            const int cur = kt & 1;
-            if (kt + 1 < nk) {
+            // stage kt has landed once at most (stages issued after it) x 8 loads are outstanding
+            const int later = min(kStages - 2, nk - 1 - kt);
+            if (later >= 2) SC2_WAIT_BARRIER(16);
+            else if (later == 1) SC2_WAIT_BARRIER(8);
+            else SC2_WAIT_BARRIER(0);
+            if (kt + kStages - 1 < nk) issue(kt + kStages - 1);
+            const uint8_t *As = smem + (kt % kStages) * kStageBytes, *Bs = As + kMatBytes;
 #pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    stage[q] = *reinterpret_cast<const v4i *>(gsrc[q] + (int64_t)(kt + 1) * kKT);
-            }
-            const uint8_t *la = &lds[cur][0][0], *lbm = &lds[cur][1][0];
+            for (int ks = 0; ks < 2; ++ks) {
+                const int fo = ks ? foff1 : foff0;
+                v4i fa[4], fb[4];
 #pragma unroll
-            for (int ks = 0; ks < kKT / 32; ++ks) {
-                v4i fa[2], fb[2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x) {
-                    fa[x] = *reinterpret_cast<const v4i *>(la + (arow + 32 * x) * kLdsStride + ks * 32 + koff);
-                    fb[x] = *reinterpret_cast<const v4i *>(lbm + (brow + 32 * x) * kLdsStride + ks * 32 + koff);
+                for (int x = 0; x < 4; ++x) {
+                    fa[x] = *reinterpret_cast<const v4i *>(As + (wm * 128 + x * 32) * kBK + fo);
+                    fb[x] = *reinterpret_cast<const v4i *>(Bs + (wn * 128 + x * 32) * kBK + fo);
                 }
 #pragma unroll
-                for (int x = 0; x < 2; ++x)
+                for (int x = 0; x < 4; ++x)
 #pragma unroll
-                    for (int y = 0; y < 2; ++y)
+                    for (int y = 0; y < 4; ++y)
                         acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[x], fb[y], acc[x][y], 0, 0, 0);
             }
-            if (kt + 1 < nk) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) *reinterpret_cast<v4i *>(&lds[cur ^ 1][0][0] + ldsoff[q]) = stage[q];
-            }
-            __syncthreads();
         }
-        // epilogue: lane holds column (lane & 31) and rows 8*(r/4) + 4*(lane/32) + r%4 of each 32 x 32 block
-        uint16_t *Gb = w.G + d.g_off;
+        __syncthreads();   // no stage is read any more: the ring becomes the tile T[256][256] (uint16)
+        // lane holds column (lane & 31) and rows 8*(r/4) + 4*(lane/32) + r%4 of each 32 x 32 block
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < 4; ++y)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int64_t i = (int64_t)bi * kSc2Tile + wm * 64 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    const int64_t j = (int64_t)bj * kSc2Tile + wn * 64 + y * 32 + (lane & 31);
-                    if (i < j && j < d.n) {
-                        const int32_t v = Cb[i * npad + j] ? acc[x][y][r] : 0;
-                        Gb[i * npad + j] = (uint16_t)v;
-                        if (w.learned && v > 0) {
-                            int32_t *ri = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
-                            int32_t *rj = w.rowstat + ((int64_t)b * w.max_n + j) * 20;
-                            atomicAdd(ri + 1, v);
-                            atomicAdd(rj + 1, v);
-                            atomicMax(ri + 2, v);
-                            atomicMax(rj + 2, v);
-                        }
+                    const int lr = wm * 128 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    const int lc = wn * 128 + y * 32 + (lane & 31);
+                    T[lr * kSc2Tile + lc] = (uint16_t)acc[x][y][r];
+                }
+        __syncthreads();
+        int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + (item - pre[b]) % kHistGroups) * w.max_n;
+        int32_t *rowmax = w.rowmax + (int64_t)b * w.max_n;
+        int32_t *rstat = w.rowstat + (int64_t)b * w.max_n * 20;
+        uint16_t *Gb = w.G + d.g_off;
+        // thread t: column chunk cc = t % 32 (8 columns) of rows lr = 8k + t / 32, k = 0..31, in four
+        // batches of eight rows; the C_ij bytes of the next batch are in flight while one is processed
+        const int cc = tid & 31;
+        const int64_t j0 = (int64_t)bj * kSc2Tile + cc * 8;
+        const uint8_t *crow = Cb + ((int64_t)bi * kSc2Tile + (tid >> 5)) * npad + j0;
+        uint2 cur[8], nxt[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cur[q] = *reinterpret_cast<const uint2 *>(crow + (int64_t)(q * 8) * npad);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            if (kb < 3) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    nxt[q] = *reinterpret_cast<const uint2 *>(crow + (int64_t)(((kb + 1) * 8 + q) * 8) * npad);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int lr = (kb * 8 + q) * 8 + (tid >> 5);
+                const int64_t i = (int64_t)bi * kSc2Tile + lr;
+                uint4 *tp = reinterpret_cast<uint4 *>(&T[lr * kSc2Tile + cc * 8]);
+                const uint4 tv = *tp;
+                const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w}, cw[2] = {cur[q].x, cur[q].y};
+                uint32_t ow[4] = {0, 0, 0, 0};
+                int rmax = 0, rsum = 0, nvalid = 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int64_t j = j0 + e;
+                    const bool valid = i < j && j < d.n;
+                    const int c = (cw[e >> 2] >> (8 * (e & 3))) & 0xFF;
+                    const int v = (valid && c) ? (int)((tw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) : 0;
+                    nvalid += valid;
+                    ow[e >> 1] |= (uint32_t)v << (16 * (e & 1));
+                    if (v > 0) {
+                        if (v < kHistLdsBins) atomicAdd(&hist[v], 1);
+                        else atomicAdd(&gh[v], 1);
+                    }
+                    rmax = max(rmax, v);
+                    rsum += v;
+                }
+                *tp = make_uint4(ow[0], ow[1], ow[2], ow[3]);   // the masked tile, for the learned column pass
+                if (nvalid == 8) {
+                    *reinterpret_cast<uint4 *>(Gb + i * npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                } else if (nvalid > 0) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int64_t j = j0 + e;
+                        if (i < j && j < d.n) Gb[i * npad + j] = (uint16_t)(ow[e >> 1] >> (16 * (e & 1)));
                     }
                 }
+#pragma unroll
+                for (int o = 16; o > 0; o >>= 1) {
+                    rmax = max(rmax, __shfl_xor(rmax, o, 64));
+                    rsum += __shfl_xor(rsum, o, 64);
+                }
+                if ((tid & 31) == 0 && rmax > 0) {
+                    atomicMax(&rowmax[i], rmax);
+                    if (w.learned) {
+                        atomicAdd(&rstat[i * 20 + 1], rsum);
+                        atomicMax(&rstat[i * 20 + 2], rmax);
+                    }
+                }
+            }
+            if (kb < 3) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
+            }
+        }
+        if (w.learned) {   // column j of the upper tile is row j of the lower one (Ghat is symmetric)
+            __syncthreads();
+            const int64_t j = (int64_t)bj * kSc2Tile + tid;
+            int csum = 0, cmax = 0;
+            for (int r = 0; r < kSc2Tile; ++r) {
+                const int v = T[r * kSc2Tile + tid];
+                csum += v;
+                cmax = max(cmax, v);
+            }
+            if (cmax > 0) {
+                atomicAdd(&rstat[j * 20 + 1], csum);
+                atomicMax(&rstat[j * 20 + 2], cmax);
+            }
+        }
+        __syncthreads();
+        const int hl = min(d.n, kHistLdsBins);
+        for (int k = tid; k < hl; k += 256) {
+            const int c = hist[k];
+            if (c) {
+                atomicAdd(&gh[k], c);
+                hist[k] = 0;
+            }
+        }
+        __syncthreads();   // T is the next item's ring
     }
 }
 
@@ -361,9 +526,9 @@ hipError_t launch_plan(const Work &w, const int32_t *offsets, int32_t n_single, 
     return hipGetLastError();
 }
 
-hipError_t launch_prep(const Work &w, int grid, hipStream_t s)
+hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prep, dim3(grid), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_prep_learned, dim3(grid), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 
@@ -375,7 +540,12 @@ hipError_t launch_compat(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sc2, dim3(grid), dim3(256), 0, s, w);
+    static bool lds_raised = false;
+    if (!lds_raised) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2), hipFuncAttributeMaxDynamicSharedMemorySize, kSc2Lds);
+        lds_raised = true;
+    }
+    hipLaunchKernelGGL(k_sc2, dim3(grid), dim3(256), kSc2Lds, s, w);
     return hipGetLastError();
 }
 

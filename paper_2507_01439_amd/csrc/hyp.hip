@@ -24,9 +24,24 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return v;
 }
 
-// One wavefront per pivot. Lanes stride over the third vertex z; each keeps
-// its KMAX best keys sorted in registers (insertion by compare-and-swap, no
-// dynamic register indexing), then K2 rounds of a wave-wide max pick the
+template <int KMAX>
+__device__ __forceinline__ void top_insert(uint64_t (&top)[KMAX], uint64_t k)
+{
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+        const uint64_t t = top[s];
+        const bool gt = k > t;
+        top[s] = gt ? k : t;
+        k = gt ? t : k;
+    }
+}
+
+// One wavefront per pivot. On the O2Graph each lane reads eight consecutive
+// weights of rows i and j with one 16-byte load each (the wave covers 512
+// third vertices per step, z > j only); on the undirected graph lanes stride
+// over z and read the lower triangle through the transpose. Each lane keeps
+// its KMAX best keys sorted in registers (compare-and-swap insertion, no
+// dynamic register indexing); K2 rounds of a wave-wide max then pick the
 // pivot's cliques in (S desc, z asc) order.
 template <int KMAX>
 __global__ void __launch_bounds__(256) k_cliques(Work w, int total)
@@ -46,28 +61,29 @@ __global__ void __launch_bounds__(256) k_cliques(Work w, int total)
             const uint16_t *G = w.G + d.g_off;
             const int64_t npad = d.npad;
             const int wij = i < j ? G[i * npad + j] : G[(int64_t)j * npad + i];
-            if (wij > 0) {
-                const int z0 = w.graph == TR_GRAPH_O2 ? j + 1 : 0;
-                for (int z = z0 + lane; z < d.n; z += 64) {
-                    int giz, gjz;
-                    if (w.graph == TR_GRAPH_O2) {
-                        giz = G[i * npad + z];
-                        gjz = G[(int64_t)j * npad + z];
-                    } else {
-                        if (z == i || z == j) continue;
-                        giz = i < z ? G[i * npad + z] : G[(int64_t)z * npad + i];
-                        gjz = j < z ? G[(int64_t)j * npad + z] : G[(int64_t)z * npad + j];
-                    }
-                    if (giz > 0 && gjz > 0) {
-                        uint64_t k = clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z);
+            if (wij > 0 && w.graph == TR_GRAPH_O2) {
+                const uint16_t *ri = G + i * npad, *rj = G + (int64_t)j * npad;
+                const int c1 = (d.n + 7) >> 3;
+                for (int c = ((j + 1) >> 3) + lane; c < c1; c += 64) {
+                    const uint4 qi = *reinterpret_cast<const uint4 *>(ri + 8 * c);
+                    const uint4 qj = *reinterpret_cast<const uint4 *>(rj + 8 * c);
+                    const uint32_t ui[4] = {qi.x, qi.y, qi.z, qi.w}, uj[4] = {qj.x, qj.y, qj.z, qj.w};
 #pragma unroll
-                        for (int s = 0; s < KMAX; ++s) {
-                            const uint64_t t = top[s];
-                            const bool gt = k > t;
-                            top[s] = gt ? k : t;
-                            k = gt ? t : k;
-                        }
+                    for (int e = 0; e < 8; ++e) {
+                        const int z = 8 * c + e;
+                        const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                        const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                        if (z > j && z < d.n && giz > 0 && gjz > 0)
+                            top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
                     }
+                }
+            } else if (wij > 0) {
+                for (int z = lane; z < d.n; z += 64) {
+                    if (z == i || z == j) continue;
+                    const int giz = i < z ? G[i * npad + z] : G[(int64_t)z * npad + i];
+                    const int gjz = j < z ? G[(int64_t)j * npad + z] : G[(int64_t)z * npad + j];
+                    if (giz > 0 && gjz > 0)
+                        top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
                 }
             }
         }
@@ -275,20 +291,21 @@ __global__ void __launch_bounds__(256) k_score(Work w)
 
 // ---------------------------------------------------------------- selection
 
-// One workgroup per pair: argmax of IN (lowest h on ties), result record and
-// the inlier mask under the selected pose.
-__global__ void __launch_bounds__(256) k_select(Work w)
+// One workgroup per pair: argmax of IN (lowest h on ties), the compatibility
+// counts summed over the pair's tiles, the result record and the inlier mask
+// under the selected pose.
+__global__ void __launch_bounds__(1024) k_select(Work w)
 {
-    __shared__ uint64_t red[4];
-    __shared__ int32_t cnt[4];
+    __shared__ uint64_t red[16];
+    __shared__ int32_t cnt[16][3];
     const int b = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const PairDesc d = w.pairs[b];
     const PairState st = w.state[b];
     uint64_t best = 0;
-    int nvalid = 0;
+    int nvalid = 0, nbnd = 0, nedge = 0;
     if (d.n > 0) {
         const int32_t *inl = w.inl + (int64_t)b * w.h_cap;
-        for (int h = threadIdx.x; h < w.H; h += 256) {
+        for (int h = threadIdx.x; h < w.H; h += 1024) {
             const int v = inl[h];
             if (v >= 0) {
                 ++nvalid;
@@ -296,15 +313,29 @@ __global__ void __launch_bounds__(256) k_select(Work w)
                 best = k > best ? k : best;
             }
         }
+        const int32_t *pre = w.pre + kCompat * w.pre_stride;
+        for (int t = pre[b] + threadIdx.x; t < pre[b + 1]; t += 1024) {
+            nbnd += w.cnt_part[2 * (int64_t)t];
+            nedge += w.cnt_part[2 * (int64_t)t + 1];
+        }
     }
     best = wave_max_u64(best);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nvalid += __shfl_xor(nvalid, o, 64);
-    if (lane == 0) { red[wv] = best; cnt[wv] = nvalid; }
+    for (int o = 32; o > 0; o >>= 1) {
+        nvalid += __shfl_xor(nvalid, o, 64);
+        nbnd += __shfl_xor(nbnd, o, 64);
+        nedge += __shfl_xor(nedge, o, 64);
+    }
+    if (lane == 0) { red[wv] = best; cnt[wv][0] = nvalid; cnt[wv][1] = nbnd; cnt[wv][2] = nedge; }
     __syncthreads();
-    best = red[0];
-    nvalid = cnt[0] + cnt[1] + cnt[2] + cnt[3];
-    for (int k = 1; k < 4; ++k) best = red[k] > best ? red[k] : best;
+    best = 0;
+    nvalid = nbnd = nedge = 0;
+    for (int k = 0; k < 16; ++k) {
+        best = red[k] > best ? red[k] : best;
+        nvalid += cnt[k][0];
+        nbnd += cnt[k][1];
+        nedge += cnt[k][2];
+    }
     const int hbest = best ? (int)(0xFFFFFFFFu - (uint32_t)best) : -1;
     float ps[12];
     if (hbest >= 0) {
@@ -328,15 +359,15 @@ __global__ void __launch_bounds__(256) k_select(Work w)
         else if (hbest < 0) status = TR_ERR_NO_HYPOTHESIS;
         else if (st.fallback) status = TR_WARN_SCORER_FALLBACK;
         r.status = status;
-        r.n_boundary_pairs = st.n_boundary;
+        r.n_boundary_pairs = nbnd;
         r.n_pivots = d.n > 0 ? min(w.k1, d.kpiv) : 0;
-        r.n_edges = st.n_edges;
+        r.n_edges = nedge;
         r.reserved = 0;
         w.out[b] = r;
     }
     if (w.masks && d.n > 0) {
         const float th2 = w.theta * w.theta;
-        for (int k = threadIdx.x; k < d.n; k += 256) {
+        for (int k = threadIdx.x; k < d.n; k += 1024) {
             const int64_t g = d.pt_off + k;
             const bool in = hbest >= 0 && residual2(ps, w.src[3 * g], w.src[3 * g + 1], w.src[3 * g + 2], w.dst[3 * g],
                                                     w.dst[3 * g + 1], w.dst[3 * g + 2]) <= th2;
@@ -372,7 +403,7 @@ hipError_t launch_score(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_select(const Work &w, int B, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_select, dim3(B), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_select, dim3(B), dim3(1024), 0, s, w);
     return hipGetLastError();
 }
 

@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(1024) k_reorder(Work w)
     const PairDesc d = w.pairs[b];
     const int K = d.kpiv;
     const bool fb = w.state[b].fallback != 0;
-    int P = 1;
+    int P = 64;
     while (P < K) P <<= 1;
     const int32_t *pl = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
     const float *sc = w.scores + (int64_t)b * w.max_n;
@@ -150,18 +150,7 @@ __global__ void __launch_bounds__(1024) k_reorder(Work w)
         keys[r] = k;
     }
     __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < P / 2; t += 1024) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t a = keys[lo], c = keys[hi];
-                if ((a > c) == up) { keys[lo] = c; keys[hi] = a; }
-            }
-            __syncthreads();
-        }
-    }
+    bitonic_sort_lds(keys, P);
     int32_t *out = w.pivots + (int64_t)b * w.piv_stride * 3;
     for (int p = threadIdx.x; p < w.k1; p += 1024) {
         if (p < K) {
@@ -477,7 +466,7 @@ hipError_t launch_features(const Work &w, uint16_t *packed, int grid, hipStream_
 hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int grid, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mlp_rows, dim3(grid), dim3(256), 0, st, w, mlp.wbf16, mlp.w32);
-    int P = 1;
+    int P = 64;
     while (P < w.pool) P <<= 1;
     static bool lds_raised = false;
     if (!lds_raised) {

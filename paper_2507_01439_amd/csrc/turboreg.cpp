@@ -44,7 +44,7 @@ struct tr_handle {
     int32_t *pre = nullptr;
     uint8_t *C = nullptr;
     uint16_t *G = nullptr;
-    int32_t *hist = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
+    int32_t *ghist = nullptr, *rowmax = nullptr, *cnt_part = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
     uint64_t *cand = nullptr;
     int32_t *pivots_plain = nullptr, *pivots = nullptr, *cliques = nullptr, *inl = nullptr;
     float *poses = nullptr;
@@ -60,9 +60,14 @@ struct tr_handle {
     int32_t last_B = 0;
     hipStream_t last_stream = nullptr;
     bool last_valid = false;
-    // profiling
-    hipEvent_t ev[TR_NUM_STAGES + 1] = {};
-    bool prof_valid = false;
+    // profiling: a ring of event sets, one set per profiled call, read without
+    // stalling the stream; per-stage sums over the calls since the last read
+    static constexpr int kRing = 256;
+    std::vector<hipEvent_t> ring;          // kRing x (TR_NUM_STAGES + 1)
+    std::vector<char> ring_pending;
+    int64_t ring_next = 0;
+    double stage_sum[TR_NUM_STAGES] = {};
+    int64_t stage_calls = 0;
     // captured batches
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     std::vector<void *> allocs;
@@ -88,8 +93,9 @@ void release(tr_handle *h)
         hipGraphDestroy(g.second.first);
     }
     h->graphs.clear();
-    for (auto &e : h->ev)
+    for (auto &e : h->ring)
         if (e) hipEventDestroy(e);
+    h->ring.clear();
     mlp_release(&h->mlp);
     for (void *p : h->allocs) hipFree(p);
     h->allocs.clear();
@@ -102,7 +108,7 @@ int grid_cap(tr_handle *h, int64_t items, int per_cu)
 }
 
 Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params &p, tr_result *out,
-               uint8_t *masks, bool learned)
+               uint8_t *masks, bool learned, int32_t B, int32_t max_n)
 {
     Work w{};
     w.src = src;
@@ -122,7 +128,9 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.theta = p.inlier_thresh;
     w.C = h->C;
     w.G = h->G;
-    w.hist = h->hist;
+    w.ghist = h->ghist;
+    w.rowmax = h->rowmax;
+    w.cnt_part = h->cnt_part;
     w.rowcnt = h->rowcnt;
     w.blkcnt = h->blkcnt;
     w.nblk_stride = h->nblk_stride;
@@ -164,13 +172,14 @@ tr_status check_params(tr_handle *h, const tr_params *p)
 // The launch sequence for B pairs (offsets on the device) or one pair (n_single).
 // features_only stops after the learned features.
 tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n_single, int32_t B,
-                  int32_t max_n, bool profile, bool features_only, hipStream_t s)
+                  int32_t max_n, hipEvent_t *ev, bool features_only, hipStream_t s)
 {
+    const bool profile = ev != nullptr;
     const int64_t npad = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
-    const int64_t nb64 = npad / kCompatTile, nb128 = npad / kSc2Tile;
+    const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
     const int64_t rows_items = (int64_t)B * ((max_n + kRowsPerItem - 1) / kRowsPerItem);
     auto mark = [&](int stage) {
-        if (profile) hipEventRecord(h->ev[stage], s);
+        if (profile) hipEventRecord(ev[stage], s);
     };
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -178,11 +187,11 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     };
     mark(TR_STAGE_PLAN);
     chk(launch_plan(w, offsets, n_single, B, max_n, h->pairs, h->state, h->plan, h->pre, s));
-    chk(launch_prep(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
+    if (w.learned) chk(launch_prep_learned(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
     mark(TR_STAGE_COMPAT);
     chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 8), s));
     mark(TR_STAGE_SC2);
-    chk(launch_sc2(w, grid_cap(h, (int64_t)B * nb128 * (nb128 + 1) / 2, 2), s));
+    chk(launch_sc2(w, grid_cap(h, (int64_t)B * nbs * (nbs + 1) / 2, 1), s));
     if (features_only) return e == hipSuccess ? TR_OK : TR_ERR_HIP;
     mark(TR_STAGE_PIVOTS);
     chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
@@ -209,13 +218,45 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     return TR_OK;
 }
 
-void remember(tr_handle *h, const Work &w, int32_t B, hipStream_t s, bool profile)
+void remember(tr_handle *h, const Work &w, int32_t B, hipStream_t s)
 {
     h->last = w;
     h->last_B = B;
     h->last_stream = s;
     h->last_valid = true;
-    h->prof_valid = profile;
+}
+
+// Fold the timings of one completed event set into the per-stage sums.
+hipError_t ring_collect(tr_handle *h, int slot)
+{
+    hipEvent_t *ev = &h->ring[(size_t)slot * (TR_NUM_STAGES + 1)];
+    hipError_t e = hipEventSynchronize(ev[TR_NUM_STAGES]);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < TR_NUM_STAGES; ++k) {
+        float t = 0;
+        e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+        if (e != hipSuccess) return e;
+        h->stage_sum[k] += t;
+    }
+    h->stage_calls += 1;
+    h->ring_pending[slot] = 0;
+    return hipSuccess;
+}
+
+// Event set for the next profiled call (created on first use).
+hipEvent_t *ring_slot(tr_handle *h)
+{
+    if (h->ring.empty()) {
+        h->ring.assign((size_t)tr_handle::kRing * (TR_NUM_STAGES + 1), nullptr);
+        h->ring_pending.assign(tr_handle::kRing, 0);
+        for (auto &e : h->ring)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    }
+    const int slot = (int)(h->ring_next % tr_handle::kRing);
+    if (h->ring_pending[slot] && ring_collect(h, slot) != hipSuccess) return nullptr;
+    h->ring_pending[slot] = 1;
+    h->ring_next += 1;
+    return &h->ring[(size_t)slot * (TR_NUM_STAGES + 1)];
 }
 
 }  // namespace
@@ -275,7 +316,12 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->pre, (size_t)kNumPrefix * h->pre_stride));
     A(alloc(h, &h->C, B * nn));
     A(alloc(h, &h->G, B * nn));
-    A(alloc(h, &h->hist, B * max_n));
+    A(alloc(h, &h->ghist, B * kHistGroups * max_n));
+    A(alloc(h, &h->rowmax, B * max_n));
+    {
+        const size_t nb64 = h->npad_max / kCompatTile;
+        A(alloc(h, &h->cnt_part, B * nb64 * (nb64 + 1) / 2 * 2));
+    }
     A(alloc(h, &h->rowcnt, B * max_n * 2));
     A(alloc(h, &h->blkcnt, B * h->nblk_stride * 2));
     A(alloc(h, &h->cand, B * h->pool_cap));
@@ -288,7 +334,6 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->feat, B * max_n * 19));
     A(alloc(h, &h->scores, B * max_n));
     A(alloc(h, &h->scratch_out, B));
-    for (auto &ev : h->ev) A(hipEventCreate(&ev));
     if (e == hipSuccess) A(mlp_create(&h->mlp));
     if (e != hipSuccess) {
         std::fprintf(stderr, "turboreg: tr_create failed: %s\n", hipGetErrorString(e));
@@ -320,10 +365,12 @@ tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t 
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
     const bool profile = (p->flags & TR_FLAG_PROFILE) != 0;
-    Work w = make_work(h, src, dst, *p, out_dev, mask_dev, learned);
+    Work w = make_work(h, src, dst, *p, out_dev, mask_dev, learned, 1, n);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    st = enqueue(h, w, nullptr, n, 1, n, profile, false, s);
-    if (st == TR_OK) remember(h, w, 1, s, profile);
+    hipEvent_t *ev = nullptr;
+    if (profile && !(ev = ring_slot(h))) return TR_ERR_HIP;
+    st = enqueue(h, w, nullptr, n, 1, n, ev, false, s);
+    if (st == TR_OK) remember(h, w, 1, s);
     return st;
 }
 
@@ -337,12 +384,14 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
     const bool profile = (p->flags & TR_FLAG_PROFILE) != 0;
-    Work w = make_work(h, src, dst, *p, out_dev, masks_dev, learned);
+    Work w = make_work(h, src, dst, *p, out_dev, masks_dev, learned, B, max_n);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (profile || s == nullptr) {
         // events (and the legacy default stream) stay out of captured graphs: run eagerly
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, profile, false, s);
-        if (st == TR_OK) remember(h, w, B, s, profile);
+        hipEvent_t *ev = nullptr;
+        if (profile && !(ev = ring_slot(h))) return TR_ERR_HIP;
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, false, s);
+        if (st == TR_OK) remember(h, w, B, s);
         return st;
     }
     GraphKey key;
@@ -361,7 +410,7 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_ERR_HIP;
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, false, false, s);
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, false, s);
         hipError_t ec = hipStreamEndCapture(s, &g);
         if (st != TR_OK || ec != hipSuccess) {
             if (g) hipGraphDestroy(g);
@@ -374,7 +423,7 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
         it = h->graphs.emplace(key, std::make_pair(g, ge)).first;
     }
     if (hipGraphLaunch(it->second.second, s) != hipSuccess) return TR_ERR_HIP;
-    remember(h, w, B, s, false);
+    remember(h, w, B, s);
     return TR_OK;
 }
 
@@ -389,14 +438,14 @@ tr_status tr_features_batch(tr_handle *h, const float *src, const float *dst, co
     q.k1 = 1;
     q.k2 = 1;
     q.pool_factor = 1;
-    Work w = make_work(h, src, dst, q, h->scratch_out, nullptr, true);
+    Work w = make_work(h, src, dst, q, h->scratch_out, nullptr, true, B, max_n);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, false, true, s);
+    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, true, s);
     if (st != TR_OK) return st;
     if (launch_features(w, feat_dev, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s) !=
         hipSuccess)
         return TR_ERR_HIP;
-    remember(h, w, B, s, false);
+    remember(h, w, B, s);
     return TR_OK;
 }
 
@@ -446,14 +495,14 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
 
 tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count)
 {
-    if (!h || !ms || count < 0 || count > TR_NUM_STAGES || !h->prof_valid) return TR_ERR_INVALID_ARG;
+    if (!h || !ms || count < 0 || count > TR_NUM_STAGES) return TR_ERR_INVALID_ARG;
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
-    if (hipEventSynchronize(h->ev[TR_NUM_STAGES]) != hipSuccess) return TR_ERR_HIP;
-    for (int k = 0; k < count; ++k) {
-        float t = 0;
-        if (hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]) != hipSuccess) return TR_ERR_HIP;
-        ms[k] = t;
-    }
+    for (int slot = 0; slot < (int)h->ring_pending.size(); ++slot)
+        if (h->ring_pending[slot] && ring_collect(h, slot) != hipSuccess) return TR_ERR_HIP;
+    if (h->stage_calls == 0) return TR_ERR_INVALID_ARG;
+    for (int k = 0; k < count; ++k) ms[k] = (float)(h->stage_sum[k] / (double)h->stage_calls);
+    for (double &x : h->stage_sum) x = 0;
+    h->stage_calls = 0;
     return TR_OK;
 }
 
