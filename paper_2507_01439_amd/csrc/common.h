@@ -141,4 +141,9 @@ hipError_t launch_kabsch(const Work &w, int B, hipStream_t s);
 hipError_t launch_score(const Work &w, int grid, hipStream_t s);
 hipError_t launch_select(const Work &w, int B, hipStream_t s);
 
+// Once per process and device, before any launch (and so outside stream capture):
+// raise the dynamic-LDS limits of the kernels that need more than 64 KiB.
+hipError_t setup_graph_kernels();
+hipError_t setup_pivot_kernels();
+
 }  // namespace tr

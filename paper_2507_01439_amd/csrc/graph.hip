@@ -540,13 +540,14 @@ hipError_t launch_compat(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s)
 {
-    static bool lds_raised = false;
-    if (!lds_raised) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2), hipFuncAttributeMaxDynamicSharedMemorySize, kSc2Lds);
-        lds_raised = true;
-    }
     hipLaunchKernelGGL(k_sc2, dim3(grid), dim3(256), kSc2Lds, s, w);
     return hipGetLastError();
+}
+
+hipError_t setup_graph_kernels()
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kSc2Lds);
 }
 
 }  // namespace tr

@@ -24,6 +24,7 @@ struct MlpState {
     float *grads = nullptr;      // kGradSlots
 };
 
+hipError_t setup_mlp_kernels();
 hipError_t mlp_create(MlpState *s);
 void mlp_release(MlpState *s);
 hipError_t mlp_set(MlpState *s, const float *host);

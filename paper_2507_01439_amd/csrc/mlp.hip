@@ -386,6 +386,12 @@ hipError_t ensure_scratch(MlpState *s, int64_t m)
 
 }  // namespace
 
+hipError_t setup_mlp_kernels()
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_reorder), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               TR_MAX_POOL * (int)sizeof(uint64_t));
+}
+
 hipError_t mlp_create(MlpState *s)
 {
     hipError_t e = hipMalloc(&s->w32, sizeof(float) * TR_MLP_NPARAM);
@@ -468,12 +474,6 @@ hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int g
     hipLaunchKernelGGL(k_mlp_rows, dim3(grid), dim3(256), 0, st, w, mlp.wbf16, mlp.w32);
     int P = 64;
     while (P < w.pool) P <<= 1;
-    static bool lds_raised = false;
-    if (!lds_raised) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(k_reorder), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            TR_MAX_POOL * (int)sizeof(uint64_t));
-        lds_raised = true;
-    }
     hipLaunchKernelGGL(k_reorder, dim3(B), dim3(1024), (size_t)P * sizeof(uint64_t), st, w);
     return hipGetLastError();
 }

@@ -154,12 +154,15 @@ __global__ void __launch_bounds__(256) k_rowcount(Work w)
         const int blk = item - pre[b];
         const int c1 = (d.n + 7) >> 3;
         int sg = 0, se = 0;
+        // a row whose largest weight is below alpha holds no candidate (alpha = 0: every row does)
+        const int myrow = blk * kRowsPerItem + (lane & (kRowsPerItem - 1));
+        const int rmax = (myrow < d.n) ? w.rowmax[(int64_t)b * w.max_n + myrow] : 0;
         for (int rr = 0; rr < kRowsPerItem / 4; ++rr) {
             const int i = blk * kRowsPerItem + wv * (kRowsPerItem / 4) + rr;
             if (i >= d.n) break;
             const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
-            // a row whose largest weight is below alpha holds no candidate (alpha = 0: every row does)
-            const int cstart = (alpha > 0 && w.rowmax[(int64_t)b * w.max_n + i] < alpha) ? c1 : ((i + 1) >> 3);
+            const int rm = __shfl(rmax, wv * (kRowsPerItem / 4) + rr, 64);
+            const int cstart = (alpha > 0 && rm < alpha) ? c1 : ((i + 1) >> 3);
             int cg = 0, ce = 0;
             for (int c = cstart + lane; c < c1; c += 64) {
                 int v[8];
@@ -212,16 +215,15 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
         }
         const int64_t tg = block_sum<int64_t>(pg, lds);
         const int64_t te = block_sum<int64_t>(pe, lds);
-        if (threadIdx.x == 0) {
-            int64_t g = tg, e = te;
-            for (int rr = 0; rr < kRowsPerItem; ++rr) {
-                const int i = blk * kRowsPerItem + rr;
+        if (threadIdx.x < 64) {   // the block's row counts, loaded at once, scanned in the first wave
+            const int rr = threadIdx.x, i = blk * kRowsPerItem + rr;
+            const bool in = rr < kRowsPerItem && i < d.n;
+            const int cg = in ? w.rowcnt[((int64_t)b * w.max_n + i) * 2] : 0;
+            const int ce = in ? w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] : 0;
+            const int64_t g = tg + wave_excl_scan(cg, rr), e = te + wave_excl_scan(ce, rr);
+            if (rr < kRowsPerItem) {
                 rowpre[rr][0] = (int32_t)g;
                 rowpre[rr][1] = (int32_t)(e < 0x7fffffff ? e : 0x7fffffff);
-                if (i < d.n) {
-                    g += w.rowcnt[((int64_t)b * w.max_n + i) * 2];
-                    e += w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1];
-                }
             }
         }
         __syncthreads();
@@ -275,30 +277,38 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
 // ---------------------------------------------------------------- ordering
 
 // Order the K keys of one pair by (w desc, i asc, j asc) and write (i, j, w).
-__global__ void __launch_bounds__(1024) k_sort(Work w)
+// Keys are distinct, so a key's rank is the number of smaller keys. One
+// single-wave workgroup per 64 keys copies the pair's K keys into its LDS and
+// ranks its own 64 against all of them; the work of one pair is spread over
+// ceil(K/64) CUs, each reading its LDS only K times per lane.
+__global__ void __launch_bounds__(64) k_sort(Work w, int blocks_per_pair)
 {
     extern __shared__ uint64_t keys[];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = w.pairs[b];
-    const int K = d.kpiv;
+    const int K = d.kpiv, lane = threadIdx.x;
     int32_t *out = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
+    if (g * 64 >= max(K, w.pool)) return;
     const uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
-    int P = 64;
-    while (P < K) P <<= 1;
-    for (int k = threadIdx.x; k < P; k += 1024) keys[k] = k < K ? cand[k] : ~0ull;
+    const int K2 = (K + 1) & ~1;
+    for (int k = lane; k < K2; k += 64) keys[k] = k < K ? cand[k] : ~0ull;
     __syncthreads();
-    bitonic_sort_lds(keys, P);
-    for (int p = threadIdx.x; p < w.pool; p += 1024) {
-        if (p < K) {
-            const uint64_t k = keys[p];
-            out[3 * p] = (int32_t)((k >> 20) & 0xFFFFF);
-            out[3 * p + 1] = (int32_t)(k & 0xFFFFF);
-            out[3 * p + 2] = (int32_t)(0xFFFFu - (uint32_t)(k >> 40));
-        } else {
-            out[3 * p] = -1;
-            out[3 * p + 1] = -1;
-            out[3 * p + 2] = 0;
+    const int p = g * 64 + lane;
+    if (p < K) {
+        const uint64_t mine = keys[p];
+        int r = 0;
+        for (int q = 0; q < K2; q += 2) {
+            const uint4 a = *reinterpret_cast<const uint4 *>(&keys[q]);
+            r += (((uint64_t)a.y << 32) | a.x) < mine;
+            r += (((uint64_t)a.w << 32) | a.z) < mine;
         }
+        out[3 * r] = (int32_t)((mine >> 20) & 0xFFFFF);
+        out[3 * r + 1] = (int32_t)(mine & 0xFFFFF);
+        out[3 * r + 2] = (int32_t)(0xFFFFu - (uint32_t)(mine >> 40));
+    } else if (p < w.pool) {
+        out[3 * p] = -1;
+        out[3 * p + 1] = -1;
+        out[3 * p + 2] = 0;
     }
 }
 
@@ -306,21 +316,23 @@ __global__ void __launch_bounds__(1024) k_sort(Work w)
 
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s)
 {
-    static bool lds_raised = false;   // up to TR_MAX_POOL keys (128 KiB) / 32767 histogram bins
-    if (!lds_raised) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(k_sort), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            TR_MAX_POOL * (int)sizeof(uint64_t));
-        hipFuncSetAttribute(reinterpret_cast<const void *>(k_thresh), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            32768 * (int)sizeof(int32_t));
-        lds_raised = true;
-    }
     hipLaunchKernelGGL(k_thresh, dim3(B), dim3(1024), (size_t)w.max_n * sizeof(int32_t), s, w);
     hipLaunchKernelGGL(k_rowcount, dim3(grid_rows), dim3(256), 0, s, w);
     hipLaunchKernelGGL(k_emit, dim3(grid_rows), dim3(256), 0, s, w);
-    int P = 64;
-    while (P < w.pool) P <<= 1;
-    hipLaunchKernelGGL(k_sort, dim3(B), dim3(1024), (size_t)P * sizeof(uint64_t), s, w);
+    const int bpp = (w.pool + 63) / 64;
+    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(64), (size_t)((w.pool + 1) & ~1) * sizeof(uint64_t), s, w, bpp);
     return hipGetLastError();
+}
+
+hipError_t setup_pivot_kernels()
+{
+    // up to TR_MAX_POOL keys (128 KiB) / 32767 histogram bins in LDS
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sort),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, TR_MAX_POOL * (int)sizeof(uint64_t));
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_thresh), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                32768 * (int)sizeof(int32_t));
+    return e;
 }
 
 }  // namespace tr

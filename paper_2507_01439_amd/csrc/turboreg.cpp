@@ -335,6 +335,9 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->scores, B * max_n));
     A(alloc(h, &h->scratch_out, B));
     if (e == hipSuccess) A(mlp_create(&h->mlp));
+    A(setup_graph_kernels());
+    A(setup_pivot_kernels());
+    A(setup_mlp_kernels());
     if (e != hipSuccess) {
         std::fprintf(stderr, "turboreg: tr_create failed: %s\n", hipGetErrorString(e));
         release(h);
