@@ -1,13 +1,15 @@
 #!/usr/bin/env python
 """Throughput of the TurboReg hot path on one MI355X.
 
-A step is one whole registration (compatibility graph, SC2 weights, pivots,
-TurboCliques, Kabsch fits, inlier scoring, selection) of one synthetic pair of
-the indoor N = 5000 workload (5% inliers, sigma 2 cm, tau = theta = 0.1 m,
-K1 = 1000, K2 = 2), inputs already resident in device memory. Prints one JSON
-line: registrations/s, per-stage times from HIP events recorded on the
-library's stream, the roofline of the dominant kernel, and the CPU oracle timed
-on a bounded sample of the same workload.
+Default workload (the metric's): one synthetic pair per step of the indoor
+N = 5000 set (5% inliers, sigma 2 cm, tau = theta = 0.1 m, K1 = 1000, K2 = 2),
+a step being one whole registration (compatibility graph, SC2 weights, pivots,
+TurboCliques, Kabsch fits, inlier scoring, selection) with inputs resident in
+device memory. Other workloads (--workload): indoor_n1000; batch256 (256 pairs
+of uneven N in one replayed hipGraph per step); outdoor16 (16 pairs of
+N = 20000). Prints one JSON line: registrations/s, per-stage times from HIP
+events recorded by the library on its stream, the roofline of the dominant
+kernel, and (default workload) the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -23,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "registrations/s @N=5k; learned vs plain pivots at equal success rate"
 PEAK_INT8_TOPS = 5000.0     # MI355X dense int8 MFMA, TOP/s
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E, GB/s
-PEAK_FP32_TFLOPS = 157.3    # MI355X fp32 vector (packed FMA counted), TFLOP/s
+WEIGHTS = os.path.join(ROOT, "paper_2507_01439_amd", "weights", "scorer_indoor.bin")
 
 
 def kernel_source_hash():
@@ -60,8 +62,24 @@ def cpu_baseline(pairs, cfg, budget_s):
             break
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "registrations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} pairs of the indoor N=5000 workload, whole path, one thread "
+            "sample": f"{done} pairs of the {cfg.n}-match indoor workload, whole path, one thread "
                       f"({platform.processor() or platform.machine()}, {os.cpu_count()} cores visible)"}
+
+
+def workload(name):
+    from paper_2507_01439_amd import synth
+    if name in ("indoor_n5000", "indoor_n1000"):
+        cfg = synth.CONFIGS[name]
+        idx = 1 if name == "indoor_n5000" else 0
+        return cfg, [[synth.make_pair(cfg, synth.pair_seed(idx, b))] for b in range(8)]
+    if name == "batch256":
+        cfgs = synth.batch_configs(256, seed=2, n_lo=500, n_hi=5000)
+        cfg = synth.CONFIGS["indoor_n1000"].replace(n=5000, k1=500)
+        return cfg, [[synth.make_pair(c, synth.pair_seed(2, b)) for b, c in enumerate(cfgs)]]
+    if name == "outdoor16":
+        cfg = synth.CONFIGS["outdoor_n20000"]
+        return cfg, [[synth.make_pair(cfg, synth.pair_seed(4, b)) for b in range(16)]]
+    raise SystemExit(f"unknown workload {name}")
 
 
 def main():
@@ -69,14 +87,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--pairs", type=int, default=8, help="distinct resident pairs cycled through")
+    ap.add_argument("--workload", default="indoor_n5000",
+                    choices=["indoor_n5000", "indoor_n1000", "batch256", "outdoor16"])
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
+    ap.add_argument("--learned", action="store_true", help="add the learned-vs-plain comparison (needs weights)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the batched path shards pairs across GPUs by design, but no collective path is built)",
-              file=sys.stderr)
+              "(batches would shard pairs across GPUs, but no multi-GPU path is built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -86,60 +105,86 @@ def main():
     from paper_2507_01439_amd import turboreg as T
 
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
-    cfg = synth.CONFIGS["indoor_n5000"]
-    pairs = [synth.make_pair(cfg, synth.pair_seed(1, b)) for b in range(args.pairs)]
-    dev = [(torch.from_numpy(p.src).cuda(), torch.from_numpy(p.dst).cuda()) for p in pairs]
-    reg = T.Registrar(max_n=cfg.n, max_batch=1, max_k1=cfg.k1, max_k2=cfg.k2)
-    outs = [torch.empty(80, dtype=torch.uint8, device="cuda") for _ in pairs]
-    masks = [torch.empty(cfg.n, dtype=torch.uint8, device="cuda") for _ in pairs]
+    cfg, groups = workload(args.workload)
+    B = len(groups[0])
+    max_n = max(p.src.shape[0] for g in groups for p in g)
+    reg = T.Registrar(max_n=max_n, max_batch=B, max_k1=cfg.k1, max_k2=cfg.k2)
     plain = T.params_from_config(cfg)
     prof = T.params_from_config(cfg, flags=T.TR_FLAG_PROFILE)
-    P = len(pairs)
+    dev = []
+    for g in groups:
+        ns = [p.src.shape[0] for p in g]
+        offs = np.concatenate([[0], np.cumsum(ns)]).astype(np.int32)
+        dev.append(dict(src=torch.from_numpy(np.concatenate([p.src for p in g])).cuda(),
+                        dst=torch.from_numpy(np.concatenate([p.dst for p in g])).cuda(),
+                        offs=torch.from_numpy(offs).cuda(), n=ns,
+                        out=torch.empty(80 * B, dtype=torch.uint8, device="cuda"),
+                        mask=torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")))
+    G = len(dev)
+    side = torch.cuda.Stream()   # default priority; batches replay a captured hipGraph on it
 
     def step(k, prm):
-        s, d = dev[k % P]
-        T.tr_register(reg.h, s, d, cfg.n, prm, outs[k % P], masks[k % P])
+        d = dev[k % G]
+        if B == 1:
+            T.tr_register(reg.h, d["src"], d["dst"], d["n"][0], prm, d["out"], d["mask"])
+        else:
+            T.tr_register_batch(reg.h, d["src"], d["dst"], d["offs"], B, max_n, prm, d["out"], d["mask"])
 
-    for k in range(args.warmup):
-        step(k, plain)
-    torch.cuda.synchronize()
-    # timed region: K whole registrations, per-stage HIP events recorded by the library on its stream
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record()
-    for k in range(args.steps):
+    # per-stage times: a profiled pass (eager, events recorded on the library's stream)
+    for k in range(max(2, args.warmup // 4)):
         step(k, prof)
-    ev1.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    T.tr_stage_times(reg.h)
+    nprof = max(5, min(args.steps, 50))
+    for k in range(nprof):
+        step(k, prof)
+    torch.cuda.synchronize()
     stages = T.tr_stage_times(reg.h)
+
+    # timed region: K steps, batches replayed from their hipGraph on the side stream
+    with torch.cuda.stream(side):
+        for k in range(args.warmup):
+            step(k, plain)
+        side.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(side)
+        for k in range(args.steps):
+            step(k, plain)
+        ev1.record(side)
+        side.synchronize()
+        wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    regs = args.steps * B
     ms_per_step = 1000.0 * wall / args.steps
 
-    res = [T.parse_results(o)[0] for o in outs]
-    ok = [synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p) for r, p in zip(res, pairs)]
+    res, ok = [], []
+    for g, d in zip(groups, dev):
+        r = T.parse_results(d["out"], B)
+        res += r
+        ok += [synth.success(np.array(x.R).reshape(3, 3), np.array(x.t), p) for x, p in zip(r, g)]
 
-    n = cfg.n
-    sc2_ops = float(n) * n * (n - 1)          # N(N-1)/2 outputs x N multiply-adds x 2
+    ns_all = [p.src.shape[0] for p in groups[0]]
+    sc2_ops = float(sum(float(n) * n * (n - 1) for n in ns_all))   # per launch: N(N-1)/2 outputs x N MACs x 2
     sc2_ms = stages["sc2"]
-    dominant = max(stages, key=stages.get)
     roof = {"kernel": "k_sc2 (int8 MFMA, C C^T on the upper triangle)", "bound": "mfma",
             "achieved": sc2_ops / (sc2_ms * 1e-3) / 1e12, "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-            "traffic": load_traffic("sc2_indoor_n5000_traffic.json")}
+            "traffic": load_traffic(f"sc2_{args.workload}_traffic.json")}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    compat_bytes = float(((n + 127) // 128 * 128) ** 2) + 24.0 * n
+    compat_bytes = float(sum(((n + 255) // 256 * 256) ** 2 + 24.0 * n for n in ns_all))
     line = {
-        "metric": METRIC, "value": args.steps / wall, "unit": "registrations/s", "n_gpus": 1,
+        "metric": METRIC, "value": regs / wall, "unit": "registrations/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+i8",
         "data": "synthetic",
-        "config": {"workload": "indoor_n5000", "n": n, "inlier_ratio": cfg.inlier_ratio, "sigma_m": cfg.sigma,
+        "config": {"workload": args.workload, "pairs_per_step": B, "n": ns_all[0] if B == 1 else "uneven",
+                   "inlier_ratio": cfg.inlier_ratio if B == 1 else "per pair", "sigma_m": cfg.sigma,
                    "tau_m": cfg.tau, "theta_m": cfg.theta, "k1": cfg.k1, "k2": cfg.k2, "pivots": "plain",
-                   "graph": "o2graph", "distinct_pairs": P},
+                   "graph": "o2graph", "distinct_inputs": G},
         "gpu_event_ms_per_step": gpu_ms / args.steps,
         "stages_us": {k: round(v * 1000.0, 2) for k, v in stages.items()},
-        "dominant_stage": dominant,
+        "dominant_stage": max(stages, key=stages.get),
         "roofline": roof,
         "compat_roofline": {"bound": "hbm", "achieved": compat_bytes / (stages["compat"] * 1e-3) / 1e9,
                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -147,8 +192,16 @@ def main():
         "success_rate": float(np.mean(ok)),
         "n_boundary_pairs_mean": float(np.mean([r.n_boundary_pairs for r in res])),
     }
-    if args.cpu_budget > 0:
-        line["cpu_baseline"] = cpu_baseline(pairs, cfg, args.cpu_budget)
+    if args.learned and os.path.exists(WEIGHTS) and args.workload == "indoor_n5000":
+        from paper_2507_01439_amd import eval_learned
+        lreg = T.Registrar(max_n=5000, max_batch=1, max_k1=1000, max_k2=2)
+        with open(WEIGHTS, "rb") as f:
+            T.tr_scorer_load(lreg.h, f.read())
+        _, hard = eval_learned.held_out(0, 32)
+        line["learned_vs_plain"] = eval_learned.compare(lreg, torch, hard, k1_sweep=(32, 125, 250, 500, 1000))
+        lreg.close()
+    if args.cpu_budget > 0 and args.workload in ("indoor_n5000", "indoor_n1000"):
+        line["cpu_baseline"] = cpu_baseline([g[0] for g in groups], cfg, args.cpu_budget)
     reg.close()
     print(json.dumps(line), flush=True)
 

@@ -65,6 +65,8 @@ struct Work {
     int32_t *rowmax;          // max_batch x max_n: max_{j>i} G_ij (filled by the SC2 epilogue)
     int32_t *cnt_part;        // per compatibility work item: (boundary pairs, edges)
     int32_t *rowcnt;          // max_batch x max_n x 2 (count > alpha, count == alpha)
+    uint64_t *rowseg;         // max_batch x max_n: bit s set if the row's s-th 512-column segment (counted
+                              // from its first column j > i) holds a pair of weight >= alpha
     int32_t *blkcnt;          // max_batch x nblk x 2
     int32_t nblk_stride;      // blocks of kRowsPerItem rows per pair (for max_n)
     uint64_t *cand;           // max_batch x pool_cap selection candidates (sort keys)

@@ -182,21 +182,53 @@ __device__ __forceinline__ float length32(float ax, float ay, float az)
 
 constexpr int kTileStride = 80;   // LDS byte-tile row stride (16-byte aligned rows)
 
+// Guard band of the fast compatibility test: v_sqrt_f32 is within a few ulps,
+// so |delta_fast - delta_exact| <= 2^-21 (|x| + |y|); a pair whose fast delta
+// lies within 2^-19 (|x| + |y|) + 2e-6 of tau is re-evaluated exactly, which
+// also covers every pair the boundary report counts (|delta - tau| < 1e-6).
+__device__ __forceinline__ bool near_tau(float la, float lb, float dl, float tau)
+{
+    return __builtin_fabsf(dl - tau) <= __builtin_fmaf(la + lb, 0x1p-19f, 2e-6f) || !(dl == dl);
+}
+
 // One 64 x 64 tile (bi <= bj) of C per work item. Each thread evaluates a
-// 4 x 4 block of pairs once; the tile and its transpose are staged in LDS and
-// written to both triangles with 16-byte stores, four lanes per 64-byte row
-// segment. Per-tile counts (boundary pairs, edges) go to a per-item slot, so
-// no atomics are needed; non-finite inputs are flagged by the diagonal tiles.
-__global__ void __launch_bounds__(256) k_compat(Work w)
+// 4 x 4 block of pairs once: the plain path with the hardware square root and
+// a guard band around tau (any lane with a pair inside it redoes its 16 pairs
+// with the correctly rounded square root, so decisions are identical to the
+// exact evaluation); learned mode always evaluates exactly, because its delta
+// histogram needs the exact value. The tile and its transpose are staged in
+// LDS and written to both triangles with 16-byte stores. The next item's
+// points are loaded while the current one is computed. Per-tile counts
+// (boundary pairs, edges) go to a per-item slot, so no atomics are needed;
+// non-finite inputs are flagged by the diagonal tiles, which also clear the
+// pair's weight histograms and row maxima for their rows.
+template <bool LEARNED>
+__global__ void __launch_bounds__(256, 2) k_compat(Work w)
 {
     __shared__ float px[2][64][3], py[2][64][3];
     __shared__ __attribute__((aligned(16))) uint8_t tile[2][64 * kTileStride];
-    __shared__ int32_t hrow[64][17], hcol[64][17];   // learned mode: delta histogram and degree per row / col
+    __shared__ int32_t hrow[LEARNED ? 64 : 1][17], hcol[LEARNED ? 64 : 1][17];
     __shared__ int32_t red[4][2];
     const int total = w.plan->total[kCompat], B = w.plan->B;
     const int32_t *pre = w.pre + kCompat * w.pre_stride;
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63, wv = tid >> 6;
     const float tau = w.tau, q = tau * 0.25f;
+    // prefetch registers: thread t < 128 holds point (t & 63) of side t >> 6
+    float nx[3] = {0, 0, 0}, ny[3] = {0, 0, 0};
+    auto fetch = [&](int item) {
+        if (tid < 128 && item < total) {
+            const int b = find_pair(pre, B, item);
+            const PairDesc d = w.pairs[b];
+            int bi, bj;
+            tri_decode(item - pre[b], d.npad / kCompatTile, bi, bj);
+            const int i = ((tid >> 6) ? bj : bi) * kCompatTile + (tid & 63);
+            for (int k = 0; k < 3; ++k) {
+                nx[k] = i < d.n ? w.src[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
+                ny[k] = i < d.n ? w.dst[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
+            }
+        }
+    };
+    fetch(blockIdx.x);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int b = find_pair(pre, B, item);
         const PairDesc d = w.pairs[b];
@@ -206,13 +238,10 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
         bool bad = false;
         if (tid < 128) {
             const int side = tid >> 6, r = tid & 63;
-            const int i = (side ? bj : bi) * kCompatTile + r;
             for (int k = 0; k < 3; ++k) {
-                const float xv = i < d.n ? w.src[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
-                const float yv = i < d.n ? w.dst[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
-                px[side][r][k] = xv;
-                py[side][r][k] = yv;
-                bad |= diag && side == 0 && !(isfinite(xv) && isfinite(yv));
+                px[side][r][k] = nx[k];
+                py[side][r][k] = ny[k];
+                bad |= diag && side == 0 && !(isfinite(nx[k]) && isfinite(ny[k]));
             }
         }
         if (diag) {   // the diagonal tiles clear this pair's histogram copies and row maxima for their 64 rows
@@ -222,11 +251,50 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
             }
             if (tid < 64 && bi * kCompatTile + tid < d.n) w.rowmax[(int64_t)b * w.max_n + bi * kCompatTile + tid] = 0;
         }
-        if (w.learned) {
+        if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) { hrow[k / 17][k % 17] = 0; hcol[k / 17][k % 17] = 0; }
         }
         if (__any(bad) && lane == 0) atomicOr(&w.state[b].nonfinite, 1);
         __syncthreads();
+        fetch(item + gridDim.x);
+        float dl[4][4];
+        bool need_exact = LEARNED;
+        if (!LEARNED) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int r = ty * 4 + a;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = tx * 4 + e;
+                    float s1 = (px[0][r][0] - px[1][c][0]) * (px[0][r][0] - px[1][c][0]);
+                    s1 = __builtin_fmaf(px[0][r][1] - px[1][c][1], px[0][r][1] - px[1][c][1], s1);
+                    s1 = __builtin_fmaf(px[0][r][2] - px[1][c][2], px[0][r][2] - px[1][c][2], s1);
+                    float s2 = (py[0][r][0] - py[1][c][0]) * (py[0][r][0] - py[1][c][0]);
+                    s2 = __builtin_fmaf(py[0][r][1] - py[1][c][1], py[0][r][1] - py[1][c][1], s2);
+                    s2 = __builtin_fmaf(py[0][r][2] - py[1][c][2], py[0][r][2] - py[1][c][2], s2);
+                    const float la = __builtin_amdgcn_sqrtf(s1), lb = __builtin_amdgcn_sqrtf(s2);
+                    dl[a][e] = __builtin_fabsf(la - lb);
+                    need_exact |= near_tau(la, lb, dl[a][e], tau);
+                }
+            }
+        }
+        if (__any(need_exact)) {
+            if (need_exact) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int r = ty * 4 + a;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int c = tx * 4 + e;
+                        const float lx = length32(px[0][r][0] - px[1][c][0], px[0][r][1] - px[1][c][1],
+                                                  px[0][r][2] - px[1][c][2]);
+                        const float ly = length32(py[0][r][0] - py[1][c][0], py[0][r][1] - py[1][c][1],
+                                                  py[0][r][2] - py[1][c][2]);
+                        dl[a][e] = __builtin_fabsf(lx - ly);
+                    }
+                }
+            }
+        }
         uint32_t rowbits[4] = {0, 0, 0, 0}, colbits[4] = {0, 0, 0, 0};
         int nbnd = 0, nedge = 0;
 #pragma unroll
@@ -235,23 +303,18 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int c = tx * 4 + e, j = bj * kCompatTile + c;
-                const float lx = length32(px[0][r][0] - px[1][c][0], px[0][r][1] - px[1][c][1],
-                                          px[0][r][2] - px[1][c][2]);
-                const float ly = length32(py[0][r][0] - py[1][c][0], py[0][r][1] - py[1][c][1],
-                                          py[0][r][2] - py[1][c][2]);
-                const float dl = __builtin_fabsf(lx - ly);
                 const bool live = i != j && i < d.n && j < d.n;
-                const uint32_t bit = (live && dl <= tau) ? 1u : 0u;
+                const uint32_t bit = (live && dl[a][e] <= tau) ? 1u : 0u;
                 rowbits[a] |= bit << (8 * e);
                 colbits[e] |= bit << (8 * a);
                 if (live && i < j) {
-                    nbnd += __builtin_fabsf(dl - tau) < 1e-6f;
+                    nbnd += __builtin_fabsf(dl[a][e] - tau) < 1e-6f;
                     nedge += (int)bit;
                 }
-                if (w.learned && live) {
+                if (LEARNED && live) {
                     int bin = 0;
 #pragma unroll
-                    for (int k = 1; k < 16; ++k) bin += dl >= (float)k * q;
+                    for (int k = 1; k < 16; ++k) bin += dl[a][e] >= (float)k * q;
                     atomicAdd(&hrow[r][bin], 1);
                     atomicAdd(&hrow[r][16], (int)bit);
                     if (!diag) {
@@ -279,7 +342,7 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
             *reinterpret_cast<uint4 *>(Cb + ((int64_t)bj * kCompatTile + r) * d.npad + bi * kCompatTile + c16) =
                 *reinterpret_cast<const uint4 *>(&tile[1][r * kTileStride + c16]);
         if (tid < 2) w.cnt_part[2 * (int64_t)item + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-        if (w.learned) {
+        if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) {
                 const int rr = k / 17, f = k % 17;
                 // feature slots: 0 degree, 3..18 histogram
@@ -289,7 +352,6 @@ __global__ void __launch_bounds__(256) k_compat(Work w)
                 if (!diag && j < d.n && hcol[rr][f]) atomicAdd(&w.rowstat[((int64_t)b * w.max_n + j) * 20 + slot], hcol[rr][f]);
             }
         }
-        __syncthreads();
     }
 }
 
@@ -534,7 +596,8 @@ hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_compat(const Work &w, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compat, dim3(grid), dim3(256), 0, s, w);
+    if (w.learned) hipLaunchKernelGGL(k_compat<true>, dim3(grid), dim3(256), 0, s, w);
+    else hipLaunchKernelGGL(k_compat<false>, dim3(grid), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 

@@ -64,13 +64,21 @@ __global__ void __launch_bounds__(256) k_cliques(Work w, int total)
             if (wij > 0 && w.graph == TR_GRAPH_O2) {
                 const uint16_t *ri = G + i * npad, *rj = G + (int64_t)j * npad;
                 const int c1 = (d.n + 7) >> 3;
-                for (int c = ((j + 1) >> 3) + lane; c < c1; c += 64) {
+                // two chunks per lane in flight: 1024 third vertices per wave step
+                for (int c = ((j + 1) >> 3) + lane; c < c1; c += 128) {
+                    const bool two = c + 64 < c1;
                     const uint4 qi = *reinterpret_cast<const uint4 *>(ri + 8 * c);
                     const uint4 qj = *reinterpret_cast<const uint4 *>(rj + 8 * c);
-                    const uint32_t ui[4] = {qi.x, qi.y, qi.z, qi.w}, uj[4] = {qj.x, qj.y, qj.z, qj.w};
+                    uint4 pi = make_uint4(0, 0, 0, 0), pj = make_uint4(0, 0, 0, 0);
+                    if (two) {
+                        pi = *reinterpret_cast<const uint4 *>(ri + 8 * (c + 64));
+                        pj = *reinterpret_cast<const uint4 *>(rj + 8 * (c + 64));
+                    }
+                    const uint32_t ui[8] = {qi.x, qi.y, qi.z, qi.w, pi.x, pi.y, pi.z, pi.w};
+                    const uint32_t uj[8] = {qj.x, qj.y, qj.z, qj.w, pj.x, pj.y, pj.z, pj.w};
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int z = 8 * c + e;
+                    for (int e = 0; e < 16; ++e) {
+                        const int z = 8 * (c + (e >> 3) * 64) + (e & 7);
                         const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
                         const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
                         if (z > j && z < d.n && giz > 0 && gjz > 0)
@@ -136,11 +144,41 @@ __device__ __forceinline__ void jacobi_rot(double (&A)[4][4], double (&V)[4][4])
     }
 }
 
+// 3x3 determinant of the 4x4 A with row R and column C removed.
+template <int R, int C>
+__device__ __forceinline__ double minor3(const double (&A)[4][4])
+{
+    constexpr int r0 = R == 0 ? 1 : 0, r1 = R <= 1 ? 2 : 1, r2 = R <= 2 ? 3 : 2;
+    constexpr int c0 = C == 0 ? 1 : 0, c1 = C <= 1 ? 2 : 1, c2 = C <= 2 ? 3 : 2;
+    return A[r0][c0] * (A[r1][c1] * A[r2][c2] - A[r1][c2] * A[r2][c1]) -
+           A[r0][c1] * (A[r1][c0] * A[r2][c2] - A[r1][c2] * A[r2][c0]) +
+           A[r0][c2] * (A[r1][c0] * A[r2][c1] - A[r1][c1] * A[r2][c0]);
+}
+
+// Column `col` of adj(A): entry r is (-1)^(r+col) times the minor of A without row col and column r.
+template <int col>
+__device__ __forceinline__ void adj_col(const double (&A)[4][4], double (&v)[4])
+{
+    v[0] = ((0 + col) & 1 ? -1.0 : 1.0) * minor3<col, 0>(A);
+    v[1] = ((1 + col) & 1 ? -1.0 : 1.0) * minor3<col, 1>(A);
+    v[2] = ((2 + col) & 1 ? -1.0 : 1.0) * minor3<col, 2>(A);
+    v[3] = ((3 + col) & 1 ? -1.0 : 1.0) * minor3<col, 3>(A);
+}
+
 // Least-squares rotation of three matches by Horn's unit-quaternion method
 // (J. Opt. Soc. Am. A 4(4), 1987): the rotation maximising sum (R p_a).q_a on
-// centred points is the eigenvector of the largest eigenvalue of a symmetric
-// 4x4 matrix built from M = sum p_a q_a^T. Solved in float64 by cyclic Jacobi,
-// then rounded to float32. One thread per hypothesis; IN is initialised here.
+// centred points is the unit eigenvector of the largest eigenvalue of a
+// traceless symmetric 4x4 matrix K built from M = sum p_a q_a^T.
+//
+// The eigenvalue is found as in the QCP method (Theobald, Acta Cryst. A 61,
+// 2005; Liu, Agrafiotis & Theobald, J. Comput. Chem. 31, 2010): Newton's
+// iteration on the characteristic polynomial
+//   det(lambda I - K) = lambda^4 - tr(K^2)/2 lambda^2 - tr(K^3)/3 lambda + det K
+// from E0 = (sum |p_a|^2 + sum |q_a|^2)/2, an upper bound of the root. The
+// eigenvector is the largest column of adj(K - lambda I). When that column
+// vanishes (a repeated top eigenvalue: collinear or coincident points) the
+// cyclic Jacobi method on K decides instead. float64 throughout, then R and t
+// are rounded to float32. One thread per hypothesis; IN is initialised here.
 __global__ void __launch_bounds__(256) k_kabsch(Work w, int total)
 {
     for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
@@ -169,47 +207,103 @@ __global__ void __launch_bounds__(256) k_kabsch(Work w, int total)
             }
 #pragma unroll
         for (int k = 0; k < 3; ++k) { pb[k] /= 3.0; qb[k] /= 3.0; }
-        double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, E0 = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
-            for (int r = 0; r < 3; ++r)
+            for (int r = 0; r < 3; ++r) {
+                const double pr = P[a][r] - pb[r], qr = Q[a][r] - qb[r];
+                E0 += 0.5 * (pr * pr + qr * qr);
 #pragma unroll
-                for (int s = 0; s < 3; ++s) M[r][s] += (P[a][r] - pb[r]) * (Q[a][s] - qb[s]);
+                for (int s = 0; s < 3; ++s) M[r][s] += pr * (Q[a][s] - qb[s]);
+            }
         const double Sxx = M[0][0], Sxy = M[0][1], Sxz = M[0][2], Syx = M[1][0], Syy = M[1][1], Syz = M[1][2],
                      Szx = M[2][0], Szy = M[2][1], Szz = M[2][2];
-        double A[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
+        double K[4][4] = {{Sxx + Syy + Szz, Syz - Szy, Szx - Sxz, Sxy - Syx},
                           {Syz - Szy, Sxx - Syy - Szz, Sxy + Syx, Szx + Sxz},
                           {Szx - Sxz, Sxy + Syx, -Sxx + Syy - Szz, Syz + Szy},
                           {Sxy - Syx, Szx + Sxz, Syz + Szy, -Sxx - Syy + Szz}};
-        double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
-        double scale = 0;
+        // characteristic polynomial: lambda^4 + c2 lambda^2 + c1 lambda + c0
+        double K2[4][4];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int s = 0; s < 4; ++s) scale += A[r][s] * A[r][s];
-        for (int sweep = 0; sweep < 16; ++sweep) {
-            const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[0][3] * A[0][3] + A[1][2] * A[1][2] +
-                               A[1][3] * A[1][3] + A[2][3] * A[2][3];
-            if (off <= 1e-30 * scale) break;
-            jacobi_rot<0, 1>(A, V);
-            jacobi_rot<0, 2>(A, V);
-            jacobi_rot<0, 3>(A, V);
-            jacobi_rot<1, 2>(A, V);
-            jacobi_rot<1, 3>(A, V);
-            jacobi_rot<2, 3>(A, V);
+            for (int s = 0; s < 4; ++s)
+                K2[r][s] = K[r][0] * K[0][s] + K[r][1] * K[1][s] + K[r][2] * K[2][s] + K[r][3] * K[3][s];
+        double tr2 = 0, tr3 = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            tr2 += K2[r][r];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) tr3 += K2[r][s] * K[s][r];
         }
-        int best = 0;
-        double bv = A[0][0];
+        const double detK = K[0][0] * minor3<0, 0>(K) - K[0][1] * minor3<0, 1>(K) + K[0][2] * minor3<0, 2>(K) -
+                            K[0][3] * minor3<0, 3>(K);
+        const double c2 = -0.5 * tr2, c1 = -tr3 / 3.0, c0 = detK;
+        double lam = E0;
+        for (int it = 0; it < 60; ++it) {
+            const double l2 = lam * lam;
+            const double f = (l2 + c2) * l2 + c1 * lam + c0;
+            const double fp = 2.0 * lam * (2.0 * l2 + c2) + c1;
+            if (!(fp > 0.0)) break;
+            const double step = f / fp;
+            lam -= step;
+            if (fabs(step) <= 1e-15 * fabs(lam)) break;
+        }
+        // eigenvector: the largest column of adj(K - lambda I)
+        double A[4][4];
 #pragma unroll
-        for (int k = 1; k < 4; ++k)
-            if (A[k][k] > bv) { bv = A[k][k]; best = k; }
-        double q0 = V[0][0], qx = V[1][0], qy = V[2][0], qz = V[3][0];
+        for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int k = 1; k < 4; ++k)
-            if (best == k) { q0 = V[0][k]; qx = V[1][k]; qy = V[2][k]; qz = V[3][k]; }
-        const double nq = 1.0 / sqrt(q0 * q0 + qx * qx + qy * qy + qz * qz);
-        q0 *= nq; qx *= nq; qy *= nq; qz *= nq;
+            for (int s = 0; s < 4; ++s) A[r][s] = K[r][s] - (r == s ? lam : 0.0);
+        double qv[4], best, cand[4], nn;
+        adj_col<0>(A, qv);
+        best = qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3];
+        auto take = [&]() {
+            nn = cand[0] * cand[0] + cand[1] * cand[1] + cand[2] * cand[2] + cand[3] * cand[3];
+            if (nn > best) {
+                best = nn;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) qv[r] = cand[r];
+            }
+        };
+        adj_col<1>(A, cand);
+        take();
+        adj_col<2>(A, cand);
+        take();
+        adj_col<3>(A, cand);
+        take();
+        const double scale3 = E0 * E0 * E0;
+        if (!(best > 1e-24 * scale3 * scale3) || !(best < 1e300)) {
+            // repeated top eigenvalue (or no spread at all): cyclic Jacobi on K
+            double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+            double fro = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) fro += K[r][s] * K[r][s];
+            for (int sweep = 0; sweep < 16; ++sweep) {
+                const double off = K[0][1] * K[0][1] + K[0][2] * K[0][2] + K[0][3] * K[0][3] + K[1][2] * K[1][2] +
+                                   K[1][3] * K[1][3] + K[2][3] * K[2][3];
+                if (off <= 1e-30 * fro) break;
+                jacobi_rot<0, 1>(K, V);
+                jacobi_rot<0, 2>(K, V);
+                jacobi_rot<0, 3>(K, V);
+                jacobi_rot<1, 2>(K, V);
+                jacobi_rot<1, 3>(K, V);
+                jacobi_rot<2, 3>(K, V);
+            }
+            int bi = 0;
+            double bv = K[0][0];
+#pragma unroll
+            for (int k = 1; k < 4; ++k)
+                if (K[k][k] > bv) { bv = K[k][k]; bi = k; }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (bi == k) { qv[0] = V[0][k]; qv[1] = V[1][k]; qv[2] = V[2][k]; qv[3] = V[3][k]; }
+        }
+        const double nq = 1.0 / sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
+        const double q0 = qv[0] * nq, qx = qv[1] * nq, qy = qv[2] * nq, qz = qv[3] * nq;
         const double R[9] = {q0 * q0 + qx * qx - qy * qy - qz * qz, 2 * (qx * qy - q0 * qz), 2 * (qx * qz + q0 * qy),
                              2 * (qy * qx + q0 * qz), q0 * q0 - qx * qx + qy * qy - qz * qz, 2 * (qy * qz - q0 * qx),
                              2 * (qz * qx - q0 * qy), 2 * (qz * qy + q0 * qx), q0 * q0 - qx * qx - qy * qy + qz * qz};
@@ -251,41 +345,52 @@ __device__ __forceinline__ float residual2(const float (&ps)[12], float x0, floa
     return s;
 }
 
+__device__ __forceinline__ float lane_bcast(float v, int q)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+}
+
 // Work item = 256 hypotheses x kScorePts matches of one pair. Each thread
-// holds one pose in registers and walks the matches staged in LDS (every lane
-// reads the same address: an LDS broadcast). Partial counts go to IN with one
-// integer atomic per thread, so the result does not depend on the order.
+// holds one pose in registers. The matches are the same for the whole wave:
+// each lane loads one of 64 (coalesced), and v_readlane hands every match to
+// all lanes as scalar operands, so the inner loop touches neither LDS nor
+// memory. Partial counts go to IN with one integer atomic per thread, so the
+// result does not depend on the order.
 __global__ void __launch_bounds__(256) k_score(Work w)
 {
-    __shared__ float sp[6][kScorePts];
     const int total = w.plan->total[kScore], B = w.plan->B;
     const int32_t *pre = w.pre + kScore * w.pre_stride;
     const float th2 = w.theta * w.theta;
+    const int lane = threadIdx.x & 63;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int b = find_pair(pre, B, item);
         const PairDesc d = w.pairs[b];
         const int npc = (d.n + kScorePts - 1) / kScorePts;
         const int local = item - pre[b], hb = local / npc, pc = local - hb * npc;
         const int k0 = pc * kScorePts, cnt = min(kScorePts, d.n - k0);
-        for (int t = threadIdx.x; t < cnt * 6; t += 256) {
-            const int k = t / 6, f = t - k * 6;
-            const float *base = f < 3 ? w.src : w.dst;
-            sp[f][k] = base[3 * (int64_t)(d.pt_off + k0 + k) + (f % 3)];
-        }
-        __syncthreads();
         const int h = hb * kScoreHyp + threadIdx.x;
         int32_t *inl = w.inl + (int64_t)b * w.h_cap + h;
-        if (h < w.H && *inl >= 0) {
-            float ps[12];
-            const float *pose = w.poses + ((int64_t)b * w.h_cap + h) * 12;
+        const bool live = h < w.H && *inl >= 0;
+        if (!__any(live)) continue;
+        float ps[12];
+        const float *pose = w.poses + ((int64_t)b * w.h_cap + min(h, w.H - 1)) * 12;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) ps[k] = pose[k];
-            int c = 0;
-            for (int k = 0; k < cnt; ++k)
-                c += residual2(ps, sp[0][k], sp[1][k], sp[2][k], sp[3][k], sp[4][k], sp[5][k]) <= th2;
-            if (c) atomicAdd(inl, c);
+        for (int k = 0; k < 12; ++k) ps[k] = pose[k];
+        int c = 0;
+        for (int kb = 0; kb < cnt; kb += 64) {
+            const int kk = kb + lane;
+            float m[6] = {0, 0, 0, 0, 0, 0};
+            if (kk < cnt) {
+                const int64_t g = d.pt_off + k0 + kk;
+#pragma unroll
+                for (int f = 0; f < 3; ++f) { m[f] = w.src[3 * g + f]; m[3 + f] = w.dst[3 * g + f]; }
+            }
+            const int mcount = min(64, cnt - kb);
+            for (int q = 0; q < mcount; ++q)
+                c += residual2(ps, lane_bcast(m[0], q), lane_bcast(m[1], q), lane_bcast(m[2], q),
+                               lane_bcast(m[3], q), lane_bcast(m[4], q), lane_bcast(m[5], q)) <= th2;
         }
-        __syncthreads();
+        if (live && c) atomicAdd(inl, c);
     }
 }
 

@@ -164,22 +164,30 @@ __global__ void __launch_bounds__(256) k_rowcount(Work w)
             const int rm = __shfl(rmax, wv * (kRowsPerItem / 4) + rr, 64);
             const int cstart = (alpha > 0 && rm < alpha) ? c1 : ((i + 1) >> 3);
             int cg = 0, ce = 0;
-            for (int c = cstart + lane; c < c1; c += 64) {
-                int v[8];
-                load8(row, c, v);
+            uint64_t segs = 0;
+            for (int c0 = cstart, s = 0; c0 < c1; c0 += 64, ++s) {
+                const int c = c0 + lane;
+                int hit = 0;
+                if (c < c1) {
+                    int v[8];
+                    load8(row, c, v);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int j = 8 * c + e;
-                    const bool in = j > i && j < d.n;
-                    cg += in && v[e] > alpha;
-                    ce += in && v[e] == alpha;
+                    for (int e = 0; e < 8; ++e) {
+                        const int j = 8 * c + e;
+                        const bool in = j > i && j < d.n;
+                        cg += in && v[e] > alpha;
+                        ce += in && v[e] == alpha;
+                        hit |= in && v[e] >= alpha;
+                    }
                 }
+                if (__any(hit) && s < 64) segs |= 1ull << s;
             }
             cg = wave_sum(cg);
             ce = wave_sum(ce);
             if (lane == 0) {
                 w.rowcnt[((int64_t)b * w.max_n + i) * 2] = cg;
                 w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] = ce;
+                w.rowseg[(int64_t)b * w.max_n + i] = segs;
             }
             sg += cg;
             se += ce;
@@ -239,7 +247,10 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
             const int eend = min(re + ne, st.m_eq);
             if (rg >= gend && re >= eend) continue;
             const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
-            for (int c0 = (i + 1) >> 3; c0 < c1 && (rg < gend || re < eend); c0 += 64) {
+            uint64_t segs = w.rowseg[(int64_t)b * w.max_n + i];
+            // only segments that hold a pair of weight >= alpha are read (segments past the 64th: all)
+            for (int s = 0, c0 = (i + 1) >> 3; c0 < c1 && (rg < gend || re < eend); ++s, c0 += 64) {
+                if (s < 64 && !((segs >> s) & 1)) continue;
                 const int c = c0 + lane;
                 int v[8];
                 int mg = 0, me = 0;
@@ -259,8 +270,10 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
                     for (int e = 0; e < 8; ++e) {
                         const int j = 8 * c + e;
                         if (!(j > i && j < d.n)) continue;
-                        if (v[e] > st.alpha) cand[og++] = pivot_key(v[e], i, j);
-                        else if (v[e] == st.alpha) {
+                        if (v[e] > st.alpha) {   // c_gt bounds the writes whatever G holds
+                            if (og < st.c_gt) cand[og] = pivot_key(v[e], i, j);
+                            ++og;
+                        } else if (v[e] == st.alpha) {
                             if (oe < st.m_eq) cand[st.c_gt + oe] = pivot_key(v[e], i, j);
                             ++oe;
                         }

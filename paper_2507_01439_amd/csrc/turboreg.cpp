@@ -45,7 +45,7 @@ struct tr_handle {
     uint8_t *C = nullptr;
     uint16_t *G = nullptr;
     int32_t *ghist = nullptr, *rowmax = nullptr, *cnt_part = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
-    uint64_t *cand = nullptr;
+    uint64_t *cand = nullptr, *rowseg = nullptr;
     int32_t *pivots_plain = nullptr, *pivots = nullptr, *cliques = nullptr, *inl = nullptr;
     float *poses = nullptr;
     int32_t *rowstat = nullptr;
@@ -135,6 +135,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.blkcnt = h->blkcnt;
     w.nblk_stride = h->nblk_stride;
     w.cand = h->cand;
+    w.rowseg = h->rowseg;
     w.pool_cap = h->pool_cap;
     w.pivots_plain = h->pivots_plain;
     if (learned) { w.pivots = h->pivots; w.piv_stride = h->k1_cap; }
@@ -325,6 +326,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->rowcnt, B * max_n * 2));
     A(alloc(h, &h->blkcnt, B * h->nblk_stride * 2));
     A(alloc(h, &h->cand, B * h->pool_cap));
+    A(alloc(h, &h->rowseg, B * max_n));
     A(alloc(h, &h->pivots_plain, B * h->pool_cap * 3));
     A(alloc(h, &h->pivots, B * h->k1_cap * 3));
     A(alloc(h, &h->cliques, B * h->h_cap * 3));

@@ -173,3 +173,27 @@ def test_host_argument_errors(reg):
     rc = T.lib().tr_register(reg.h, None, T._ptr(dst), 50, T.ct.byref(T.make_params(0.1, 0.1, 10, 2)),
                              T._ptr(out), None, T._stream())
     assert rc == T.TR_ERR_INVALID_ARG
+
+
+def test_compat_guard_band_stress():
+    # tau at the median delta: millions of pairs near the threshold, every decision must match exactly
+    n = 12000
+    rng = np.random.default_rng(77)
+    X = ((rng.random((n, 3)) - 0.5) * 3).astype(np.float32)
+    Y = ((rng.random((n, 3)) - 0.5) * 3).astype(np.float32)
+    s = rng.choice(n, 2000, replace=False)
+    dx = np.linalg.norm(X[s][:, None] - X[s][None], axis=2)
+    dy = np.linalg.norm(Y[s][:, None] - Y[s][None], axis=2)
+    tau = float(np.float32(np.median(np.abs(dx - dy))))
+    big = T.Registrar(max_n=n, max_batch=1, max_k1=100, max_k2=2)
+    try:
+        prm = T.make_params(tau, 0.1, k1=100, k2=2)
+        say(f"guard band stress n={n} tau={tau}")
+        r, _ = run_single(big, torch, X, Y, prm)
+        C = big.debug(T.TR_TAP_C)
+        Co, b32, _, _ = oracle.compat(X, Y, tau)
+        assert np.array_equal(C, Co), f"C differs at {np.argwhere(C != Co)[:5].tolist()}"
+        assert r.n_boundary_pairs == b32 and r.n_edges == int(Co.sum()) // 2
+        say(f"edges {r.n_edges} boundary {b32}")
+    finally:
+        big.close()
