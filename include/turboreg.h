@@ -109,7 +109,9 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst,
  * TR_MLP_NPARAM float32 (W1 64x19, b1, W2 64x64, b2, W3 1x64, b3; row-major,
  * out x in), then an FNV-1a 64-bit checksum of those bytes. */
 tr_status tr_scorer_load(tr_handle *h, const void *blob, size_t bytes);
-/* Write the current float32 master weights; *written = bytes used. */
+/* Write the current float32 master weights in that format; *written = the
+ * blob size. blob == NULL with written != NULL is a size query (TR_OK);
+ * capacity below the blob size is TR_ERR_INVALID_ARG. */
 tr_status tr_scorer_save(tr_handle *h, void *blob, size_t capacity, size_t *written);
 /* Set weights from TR_MLP_NPARAM host float32 values (same order) and reset Adam state. */
 tr_status tr_scorer_set(tr_handle *h, const float *params_host);

@@ -7,7 +7,7 @@
 
 namespace tr {
 
-constexpr int kSc2Tile = 256;     // output tile edge of the int8 MFMA SC2 kernel; npad is a multiple
+constexpr int kSc2Tile = 256;     // output tile edge of the FP4 MFMA SC2 kernel; npad is a multiple
 constexpr int kHistGroups = 16;   // SC2 tiles add their weight histograms into this many copies per pair
 constexpr int kCompatTile = 64;   // tile edge of the compatibility kernel
 constexpr int kRowsPerItem = 16;  // rows per work item of the pivot scans
@@ -25,7 +25,7 @@ struct PairDesc {
     int32_t npad;     // n rounded up to kSc2Tile
     int32_t pt_off;   // first match of this pair in src/dst
     int32_t kpiv;     // pivots to select: min(k1 or pool, n(n-1)/2)
-    int64_t c_off;    // byte offset of this pair's C in the C arena (npad x npad int8)
+    int64_t c_off;    // entry offset of this pair's C in the C arena (npad x npad E2M1, bytes = c_off / 2)
     int64_t g_off;    // element offset of this pair's G in the G arena (npad x npad uint16)
 };
 

@@ -180,7 +180,13 @@ __device__ __forceinline__ float length32(float ax, float ay, float az)
     return __builtin_sqrtf(s);
 }
 
-constexpr int kTileStride = 80;   // LDS byte-tile row stride (16-byte aligned rows)
+constexpr int kNibStride = 32;    // LDS row stride of a packed 64-column tile (two entries per byte)
+
+// Four 0/1 bytes -> four E2M1 nibbles (1.0 = 0x2, 0.0 = 0x0), byte k -> bits 4k..4k+3.
+__device__ __forceinline__ uint32_t pack_e2m1(uint32_t x)
+{
+    return ((x << 1) & 0x2u) | ((x >> 3) & 0x20u) | ((x >> 7) & 0x200u) | ((x >> 11) & 0x2000u);
+}
 
 // Guard band of the fast compatibility test: v_sqrt_f32 is within a few ulps,
 // so |delta_fast - delta_exact| <= 2^-21 (|x| + |y|); a pair whose fast delta
@@ -206,7 +212,7 @@ template <bool LEARNED>
 __global__ void __launch_bounds__(256, 2) k_compat(Work w)
 {
     __shared__ float px[2][64][3], py[2][64][3];
-    __shared__ __attribute__((aligned(16))) uint8_t tile[2][64 * kTileStride];
+    __shared__ __attribute__((aligned(16))) uint8_t tile[2][64 * kNibStride];
     __shared__ int32_t hrow[LEARNED ? 64 : 1][17], hcol[LEARNED ? 64 : 1][17];
     __shared__ int32_t red[4][2];
     const int total = w.plan->total[kCompat], B = w.plan->B;
@@ -326,21 +332,22 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
-            *reinterpret_cast<uint32_t *>(&tile[0][(ty * 4 + a) * kTileStride + tx * 4]) = rowbits[a];
+            *reinterpret_cast<uint16_t *>(&tile[0][(ty * 4 + a) * kNibStride + tx * 2]) = (uint16_t)pack_e2m1(rowbits[a]);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            *reinterpret_cast<uint32_t *>(&tile[1][(tx * 4 + e) * kTileStride + ty * 4]) = colbits[e];
+            *reinterpret_cast<uint16_t *>(&tile[1][(tx * 4 + e) * kNibStride + ty * 2]) = (uint16_t)pack_e2m1(colbits[e]);
         nbnd = wave_sum(nbnd);
         nedge = wave_sum(nedge);
         if (lane == 0) { red[wv][0] = nbnd; red[wv][1] = nedge; }
         __syncthreads();
-        uint8_t *Cb = w.C + d.c_off;
-        const int r = tid >> 2, c16 = (tid & 3) * 16;
-        *reinterpret_cast<uint4 *>(Cb + ((int64_t)bi * kCompatTile + r) * d.npad + bj * kCompatTile + c16) =
-            *reinterpret_cast<const uint4 *>(&tile[0][r * kTileStride + c16]);
+        uint8_t *Cb = w.C + d.c_off / 2;   // packed rows of npad / 2 bytes
+        const int64_t rs = d.npad / 2;
+        const int r = tid >> 2, c8 = (tid & 3) * 8;
+        *reinterpret_cast<uint2 *>(Cb + ((int64_t)bi * kCompatTile + r) * rs + bj * (kCompatTile / 2) + c8) =
+            *reinterpret_cast<const uint2 *>(&tile[0][r * kNibStride + c8]);
         if (!diag)
-            *reinterpret_cast<uint4 *>(Cb + ((int64_t)bj * kCompatTile + r) * d.npad + bi * kCompatTile + c16) =
-                *reinterpret_cast<const uint4 *>(&tile[1][r * kTileStride + c16]);
+            *reinterpret_cast<uint2 *>(Cb + ((int64_t)bj * kCompatTile + r) * rs + bi * (kCompatTile / 2) + c8) =
+                *reinterpret_cast<const uint2 *>(&tile[1][r * kNibStride + c8]);
         if (tid < 2) w.cnt_part[2 * (int64_t)item + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
         if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) {
@@ -355,20 +362,24 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
     }
 }
 
-// ---------------------------------------------------------------- Eq. 2 on int8 MFMA
+// ---------------------------------------------------------------- Eq. 2 on FP4 MFMA
 
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef int32_t v8i __attribute__((ext_vector_type(8)));
 typedef int32_t v16i __attribute__((ext_vector_type(16)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) void gvoid;
 typedef __attribute__((address_space(3))) void lvoid;
 
-constexpr int kBK = 64;                        // K bytes per pipeline stage
+constexpr int kBK = 64;                        // bytes of a packed row per pipeline stage (128 k)
 constexpr int kStages = 4;                     // LDS ring depth (three stages in flight)
 constexpr int kMatBytes = kSc2Tile * kBK;      // one operand's stage: 256 rows x 64 bytes
 constexpr int kStageBytes = 2 * kMatBytes;
 constexpr int kRingBytes = kStages * kStageBytes;   // 128 KiB; also holds the finished tile as uint16
 constexpr int kHistLdsBins = 8192;             // weights below this are histogrammed in LDS first
 constexpr int kSc2Lds = kRingBytes + kHistLdsBins * 4;   // 160 KiB
+constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then the low 16 bits of 2^23 + v
 
 // Wait until at most N vector-memory loads of this wave are outstanding, then
 // meet the other waves. The memory clobber keeps LDS reads of the new stage
@@ -379,14 +390,18 @@ constexpr int kSc2Lds = kRingBytes + kHistLdsBins * 4;   // 160 KiB
 // with bi <= bj. C is symmetric, so the product is C C^T and both MFMA
 // operands are rows of C read along k.
 //
+// C is stored as E2M1 (FP4) nibbles, 1.0 = 0x2: every product is 0 or 1 and
+// every partial sum is an integer below 2^24, so the float32 accumulation of
+// v_mfma_scale_f32_32x32x64_f8f6f4 (unit scales) is exact, and FP4 halves the
+// operand bytes of an int8 product. Accumulators start at 2^23, so a finished
+// count is read from the low 16 bits of the float without a conversion.
+//
 // Four waves in a 2 x 2 layout each own a 128 x 128 sub-tile as 4 x 4 blocks
-// of v_mfma_i32_32x32x32_i8 (int32 sums are exact: at most N - 2; the
-// accumulators live in AGPRs). Operand stages of 64 bytes of k arrive by
+// of 32 x 32 (accumulators in AGPRs). Stages of 64 bytes (128 k) arrive by
 // direct global->LDS 16-byte loads into a four-deep ring, three stages in
 // flight; a row's four 16-byte chunks are stored XOR-swizzled by (row/4) mod 4
-// so the fragment reads (ds_read_b128) are free of bank conflicts. Work items
-// are split into 8 contiguous ranges, one per XCD, so tiles that share rows of
-// C share an L2.
+// for the fragment reads (ds_read_b128). Work items are split into 8
+// contiguous ranges, one per XCD, so tiles that share rows of C share an L2.
 //
 // Epilogue: the tile is restaged in LDS as uint16 (weights are below 2^16),
 // then read row-major: masked by C_ij and i < j < n, stored with 16-byte
@@ -415,9 +430,9 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         const PairDesc d = w.pairs[b];
         int bi, bj;
         super_decode(item - pre[b], d.npad / kSc2Tile, bi, bj);
-        const uint8_t *Cb = w.C + d.c_off;
-        const int64_t npad = d.npad;
-        const int nk = d.npad / kBK;
+        const uint8_t *Cb = w.C + d.c_off / 2;
+        const int64_t rs = d.npad / 2;       // packed row bytes
+        const int nk = (int)(rs / kBK);
         // load s of a stage: row r = (s&3)*64 + wv*16 + lane/4 of operand s/4 into LDS chunk lane&3,
         // which holds the row's global chunk (lane&3) ^ ((r/4)&3)
         uint32_t goff[8];
@@ -425,7 +440,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         for (int s = 0; s < 8; ++s) {
             const int r = (s & 3) * 64 + wv * 16 + (lane >> 2);
             const int64_t row = (int64_t)((s >> 2) ? bj : bi) * kSc2Tile + r;
-            goff[s] = (uint32_t)(row * npad + 16 * ((lane & 3) ^ ((r >> 2) & 3)));
+            goff[s] = (uint32_t)(row * rs + 16 * ((lane & 3) ^ ((r >> 2) & 3)));
         }
         auto issue = [&](int kt) {
             uint8_t *dst = smem + (kt % kStages) * kStageBytes + wv * 1024;
@@ -435,11 +450,13 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 __builtin_amdgcn_global_load_lds((gvoid *)(src + goff[s]),
                                                  (lvoid *)(dst + (s >> 2) * kMatBytes + (s & 3) * 4096), 16, 0, 0);
         };
-        v16i acc[4][4];
+        v16f acc[4][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] = (v16i){};
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[x][y][r] = kAccBias;
 #pragma unroll
         for (int kt = 0; kt < kStages - 1; ++kt)
             if (kt < nk) issue(kt);
@@ -463,74 +480,102 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
 #pragma unroll
                 for (int x = 0; x < 4; ++x)
 #pragma unroll
-                    for (int y = 0; y < 4; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[x], fb[y], acc[x][y], 0, 0, 0);
+                    for (int y = 0; y < 4; ++y) {
+                        // 32 FP4 values of k per lane: 16 bytes, the upper half of the operand is unused
+                        const v8i a8 = {fa[x][0], fa[x][1], fa[x][2], fa[x][3], 0, 0, 0, 0};
+                        const v8i b8 = {fb[y][0], fb[y][1], fb[y][2], fb[y][3], 0, 0, 0, 0};
+                        acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[x][y], 4, 4, 0, 127,
+                                                                                     0, 127);
+                    }
             }
         }
         __syncthreads();   // no stage is read any more: the ring becomes the tile T[256][256] (uint16)
-        // lane holds column (lane & 31) and rows 8*(r/4) + 4*(lane/32) + r%4 of each 32 x 32 block
+        // lane holds column (lane & 31) and rows 8*(r/4) + 4*(lane/32) + r%4 of each 32 x 32 block;
+        // the whole vector is reinterpreted before the low halves are taken
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int y = 0; y < 4; ++y)
+            for (int y = 0; y < 4; ++y) {
+                const v16i ai = __builtin_bit_cast(v16i, acc[x][y]);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int lr = wm * 128 + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
                     const int lc = wn * 128 + y * 32 + (lane & 31);
-                    T[lr * kSc2Tile + lc] = (uint16_t)acc[x][y][r];
+                    T[lr * kSc2Tile + lc] = (uint16_t)ai[r];
                 }
+            }
         __syncthreads();
         int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + (item - pre[b]) % kHistGroups) * w.max_n;
         int32_t *rowmax = w.rowmax + (int64_t)b * w.max_n;
         int32_t *rstat = w.rowstat + (int64_t)b * w.max_n * 20;
         uint16_t *Gb = w.G + d.g_off;
+        // every pair of the tile is in the strict upper triangle and below n: no per-entry test
+        const bool interior = bi < bj && (bj + 1) * kSc2Tile <= d.n;
         // thread t: column chunk cc = t % 32 (8 columns) of rows lr = 8k + t / 32, k = 0..31, in four
-        // batches of eight rows; the C_ij bytes of the next batch are in flight while one is processed
+        // batches of eight rows; the packed C_ij of the next batch are in flight while one is processed
         const int cc = tid & 31;
-        const int64_t j0 = (int64_t)bj * kSc2Tile + cc * 8;
-        const uint8_t *crow = Cb + ((int64_t)bi * kSc2Tile + (tid >> 5)) * npad + j0;
-        uint2 cur[8], nxt[8];
+        const int j0 = bj * kSc2Tile + cc * 8;
+        const uint8_t *crow = Cb + ((int64_t)bi * kSc2Tile + (tid >> 5)) * rs + j0 / 2;
+        uint32_t cur[8], nxt[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) cur[q] = *reinterpret_cast<const uint2 *>(crow + (int64_t)(q * 8) * npad);
+        for (int q = 0; q < 8; ++q) cur[q] = *reinterpret_cast<const uint32_t *>(crow + (int64_t)(q * 8) * rs);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             if (kb < 3) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    nxt[q] = *reinterpret_cast<const uint2 *>(crow + (int64_t)(((kb + 1) * 8 + q) * 8) * npad);
+                    nxt[q] = *reinterpret_cast<const uint32_t *>(crow + (int64_t)(((kb + 1) * 8 + q) * 8) * rs);
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int lr = (kb * 8 + q) * 8 + (tid >> 5);
-                const int64_t i = (int64_t)bi * kSc2Tile + lr;
+                const int i = bi * kSc2Tile + lr;
                 uint4 *tp = reinterpret_cast<uint4 *>(&T[lr * kSc2Tile + cc * 8]);
                 const uint4 tv = *tp;
-                const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w}, cw[2] = {cur[q].x, cur[q].y};
-                uint32_t ow[4] = {0, 0, 0, 0};
-                int rmax = 0, rsum = 0, nvalid = 0;
+                const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w};
+                const uint32_t cb = cur[q] >> 1;   // C of column e at bit 4e
+                uint32_t ow[4];
+                if (interior) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t lo = (cb >> (8 * k)) & 1u, hi = (cb >> (8 * k + 4)) & 1u;
+                        ow[k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int ja = j0 + 2 * k, jb = ja + 1;
+                        const uint32_t lo = ((cb >> (8 * k)) & 1u) & (uint32_t)(i < ja && ja < d.n);
+                        const uint32_t hi = ((cb >> (8 * k + 4)) & 1u) & (uint32_t)(i < jb && jb < d.n);
+                        ow[k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
+                    }
+                }
+                int rsum = 0;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int64_t j = j0 + e;
-                    const bool valid = i < j && j < d.n;
-                    const int c = (cw[e >> 2] >> (8 * (e & 3))) & 0xFF;
-                    const int v = (valid && c) ? (int)((tw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) : 0;
-                    nvalid += valid;
-                    ow[e >> 1] |= (uint32_t)v << (16 * (e & 1));
+                    const int v = (int)((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
                     if (v > 0) {
                         if (v < kHistLdsBins) atomicAdd(&hist[v], 1);
                         else atomicAdd(&gh[v], 1);
                     }
-                    rmax = max(rmax, v);
                     rsum += v;
                 }
+                const u16x2 m2 = __builtin_elementwise_max(
+                    __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[0]), __builtin_bit_cast(u16x2, ow[1])),
+                    __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[2]), __builtin_bit_cast(u16x2, ow[3])));
+                int rmax = max((int)m2.x, (int)m2.y);
                 *tp = make_uint4(ow[0], ow[1], ow[2], ow[3]);   // the masked tile, for the learned column pass
-                if (nvalid == 8) {
-                    *reinterpret_cast<uint4 *>(Gb + i * npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-                } else if (nvalid > 0) {
+                if (interior) {
+                    *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                } else if (i < d.n && j0 + 7 > i && j0 < d.n) {
+                    if (j0 > i && j0 + 8 <= d.n) {
+                        *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int64_t j = j0 + e;
-                        if (i < j && j < d.n) Gb[i * npad + j] = (uint16_t)(ow[e >> 1] >> (16 * (e & 1)));
+                        for (int e = 0; e < 8; ++e) {
+                            const int j = j0 + e;
+                            if (i < j && j < d.n) Gb[(int64_t)i * d.npad + j] = (uint16_t)(ow[e >> 1] >> (16 * (e & 1)));
+                        }
                     }
                 }
 #pragma unroll
@@ -553,7 +598,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         }
         if (w.learned) {   // column j of the upper tile is row j of the lower one (Ghat is symmetric)
             __syncthreads();
-            const int64_t j = (int64_t)bj * kSc2Tile + tid;
+            const int j = bj * kSc2Tile + tid;
             int csum = 0, cmax = 0;
             for (int r = 0; r < kSc2Tile; ++r) {
                 const int v = T[r * kSc2Tile + tid];

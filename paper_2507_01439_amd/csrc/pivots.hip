@@ -39,6 +39,39 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane)
     return x - v;
 }
 
+// Inclusive prefix sum over the 64 lanes: shifts by 1, 2, 4, 8 inside each
+// 16-lane row, then the last lane of row 0 is added to row 1 and of row 2 to
+// row 3, then lane 31 to rows 2 and 3 (DPP row_shr / row_bcast, no LDS).
+__device__ __forceinline__ int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+// Counts of one 16-byte chunk of a G row: pairs (i, j), j in 8c .. 8c+7 inside
+// i < j < n, heavier than alpha (low half) and equal to it (high half).
+__device__ __forceinline__ int chunk_counts(const uint4 q, int c, int i, int n, int alpha, bool &hit)
+{
+    const uint32_t u[4] = {q.x, q.y, q.z, q.w};
+    int g = 0, e = 0;
+    hit = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int v = (int)((u[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
+        const int j = 8 * c + k;
+        const bool in = j > i && j < n;
+        g += in && v > alpha;
+        e += in && v == alpha;
+        hit |= in && v >= alpha;
+    }
+    return g | (e << 16);
+}
+
 template <typename T>
 __device__ T block_sum(T v, T *lds)
 {
@@ -161,29 +194,29 @@ __global__ void __launch_bounds__(256) k_rowcount(Work w)
             const int i = blk * kRowsPerItem + wv * (kRowsPerItem / 4) + rr;
             if (i >= d.n) break;
             const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
-            const int rm = __shfl(rmax, wv * (kRowsPerItem / 4) + rr, 64);
-            const int cstart = (alpha > 0 && rm < alpha) ? c1 : ((i + 1) >> 3);
-            int cg = 0, ce = 0;
+            const int rm = __builtin_amdgcn_readlane(rmax, wv * (kRowsPerItem / 4) + rr);
+            const int c_lo = (i + 1) >> 3;
+            const int cstart = (alpha > 0 && rm < alpha) ? c1 : c_lo;
+            int cnt = 0;
             uint64_t segs = 0;
-            for (int c0 = cstart, s = 0; c0 < c1; c0 += 64, ++s) {
-                const int c = c0 + lane;
-                int hit = 0;
-                if (c < c1) {
-                    int v[8];
-                    load8(row, c, v);
+            // segments of 64 chunks (512 columns), eight 16-byte loads in flight per lane
+            for (int c0 = cstart; c0 < c1; c0 += 512) {
+                uint4 q[8];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int j = 8 * c + e;
-                        const bool in = j > i && j < d.n;
-                        cg += in && v[e] > alpha;
-                        ce += in && v[e] == alpha;
-                        hit |= in && v[e] >= alpha;
-                    }
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + 64 * u + lane;
+                    q[u] = c < c1 ? *reinterpret_cast<const uint4 *>(row + 8 * c) : make_uint4(0, 0, 0, 0);
                 }
-                if (__any(hit) && s < 64) segs |= 1ull << s;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + 64 * u + lane;
+                    bool hit = false;
+                    if (c < c1) cnt += chunk_counts(q[u], c, i, d.n, alpha, hit);
+                    if (__any(hit)) segs |= 1ull << ((c0 - c_lo) / 64 + u);   // at most 64 segments (N < 32768)
+                }
             }
-            cg = wave_sum(cg);
-            ce = wave_sum(ce);
+            cnt = __builtin_amdgcn_readlane(wave_incl_scan(cnt), 63);
+            const int cg = cnt & 0xFFFF, ce = cnt >> 16;
             if (lane == 0) {
                 w.rowcnt[((int64_t)b * w.max_n + i) * 2] = cg;
                 w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] = ce;
@@ -247,40 +280,50 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
             const int eend = min(re + ne, st.m_eq);
             if (rg >= gend && re >= eend) continue;
             const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
-            uint64_t segs = w.rowseg[(int64_t)b * w.max_n + i];
-            // only segments that hold a pair of weight >= alpha are read (segments past the 64th: all)
-            for (int s = 0, c0 = (i + 1) >> 3; c0 < c1 && (rg < gend || re < eend); ++s, c0 += 64) {
-                if (s < 64 && !((segs >> s) & 1)) continue;
-                const int c = c0 + lane;
-                int v[8];
-                int mg = 0, me = 0;
-                if (c < c1) {
-                    load8(row, c, v);
+            uint64_t todo = w.rowseg[(int64_t)b * w.max_n + i];
+            const int c_lo = (i + 1) >> 3;
+            // only segments that hold a pair of weight >= alpha are read, eight at a time
+            while (todo && (rg < gend || re < eend)) {
+                uint4 q[8];
+                int cs[8];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int j = 8 * c + e;
-                        const bool in = j > i && j < d.n;
-                        mg += in && v[e] > st.alpha;
-                        me += in && v[e] == st.alpha;
+                for (int u = 0; u < 8; ++u) {
+                    int c = -1;
+                    if (todo) {
+                        c = c_lo + 64 * __builtin_ctzll(todo) + lane;
+                        todo &= todo - 1;
                     }
+                    cs[u] = c;
+                    q[u] = (c >= 0 && c < c1) ? *reinterpret_cast<const uint4 *>(row + 8 * c) : make_uint4(0, 0, 0, 0);
                 }
-                int og = rg + wave_excl_scan(mg, lane), oe = re + wave_excl_scan(me, lane);
-                if (mg | me) {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int j = 8 * c + e;
-                        if (!(j > i && j < d.n)) continue;
-                        if (v[e] > st.alpha) {   // c_gt bounds the writes whatever G holds
-                            if (og < st.c_gt) cand[og] = pivot_key(v[e], i, j);
-                            ++og;
-                        } else if (v[e] == st.alpha) {
-                            if (oe < st.m_eq) cand[st.c_gt + oe] = pivot_key(v[e], i, j);
-                            ++oe;
+                for (int u = 0; u < 8; ++u) {
+                    const int c = cs[u];
+                    if (__builtin_amdgcn_readfirstlane(c) < 0) break;   // no segment left (same on every lane)
+                    bool hit;
+                    const int cnt = c < c1 ? chunk_counts(q[u], c, i, d.n, st.alpha, hit) : 0;
+                    const int incl = wave_incl_scan(cnt);
+                    const int excl = incl - cnt, tot = __builtin_amdgcn_readlane(incl, 63);
+                    if (cnt) {
+                        int og = rg + (excl & 0xFFFF), oe = re + (excl >> 16);
+                        const uint32_t uw[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int j = 8 * c + e;
+                            if (!(j > i && j < d.n)) continue;
+                            const int v = (int)((uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                            if (v > st.alpha) {   // c_gt bounds the writes whatever G holds
+                                if (og < st.c_gt) cand[og] = pivot_key(v, i, j);
+                                ++og;
+                            } else if (v == st.alpha) {
+                                if (oe < st.m_eq) cand[st.c_gt + oe] = pivot_key(v, i, j);
+                                ++oe;
+                            }
                         }
                     }
+                    rg += tot & 0xFFFF;
+                    re += tot >> 16;
                 }
-                rg += wave_sum(mg);
-                re += wave_sum(me);
             }
         }
         __syncthreads();
@@ -290,34 +333,47 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
 // ---------------------------------------------------------------- ordering
 
 // Order the K keys of one pair by (w desc, i asc, j asc) and write (i, j, w).
-// Keys are distinct, so a key's rank is the number of smaller keys. One
-// single-wave workgroup per 64 keys copies the pair's K keys into its LDS and
-// ranks its own 64 against all of them; the work of one pair is spread over
-// ceil(K/64) CUs, each reading its LDS only K times per lane.
-__global__ void __launch_bounds__(64) k_sort(Work w, int blocks_per_pair)
+// Keys are distinct, so a key's rank is the number of smaller keys. Each
+// 256-thread workgroup copies the pair's K keys into its LDS and ranks 64 of
+// them: wave v counts the smaller keys in its quarter of the list with eight
+// 16-byte broadcast reads in flight, and the four partial counts are summed.
+// The work of one pair is spread over ceil(K/64) CUs.
+__global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
 {
     extern __shared__ uint64_t keys[];
+    __shared__ int32_t part[4][64];
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = w.pairs[b];
-    const int K = d.kpiv, lane = threadIdx.x;
+    const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     int32_t *out = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
     if (g * 64 >= max(K, w.pool)) return;
     const uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
-    const int K2 = (K + 1) & ~1;
-    for (int k = lane; k < K2; k += 64) keys[k] = k < K ? cand[k] : ~0ull;
+    const int K16 = (K + 15) & ~15;   // padded with keys larger than any real one
+    for (int k = tid; k < K16; k += 256) keys[k] = k < K ? cand[k] : ~0ull;
     __syncthreads();
     const int p = g * 64 + lane;
-    if (p < K) {
-        const uint64_t mine = keys[p];
-        int r = 0;
-        for (int q = 0; q < K2; q += 2) {
-            const uint4 a = *reinterpret_cast<const uint4 *>(&keys[q]);
-            r += (((uint64_t)a.y << 32) | a.x) < mine;
-            r += (((uint64_t)a.w << 32) | a.z) < mine;
+    const uint64_t mine = p < K ? keys[p] : 0;
+    const int per = ((K16 / 16 + 3) / 4) * 16;
+    const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
+    int r = 0;
+    for (int q = q0; q < q1; q += 16) {
+        uint4 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const uint4 *>(&keys[q + 2 * u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            r += (((uint64_t)a[u].y << 32) | a[u].x) < mine;
+            r += (((uint64_t)a[u].w << 32) | a[u].z) < mine;
         }
-        out[3 * r] = (int32_t)((mine >> 20) & 0xFFFFF);
-        out[3 * r + 1] = (int32_t)(mine & 0xFFFFF);
-        out[3 * r + 2] = (int32_t)(0xFFFFu - (uint32_t)(mine >> 40));
+    }
+    part[wv][lane] = r;
+    __syncthreads();
+    if (wv != 0) return;
+    if (p < K) {
+        const int rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+        out[3 * rk] = (int32_t)((mine >> 20) & 0xFFFFF);
+        out[3 * rk + 1] = (int32_t)(mine & 0xFFFFF);
+        out[3 * rk + 2] = (int32_t)(0xFFFFu - (uint32_t)(mine >> 40));
     } else if (p < w.pool) {
         out[3 * p] = -1;
         out[3 * p + 1] = -1;
@@ -333,7 +389,7 @@ hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s)
     hipLaunchKernelGGL(k_rowcount, dim3(grid_rows), dim3(256), 0, s, w);
     hipLaunchKernelGGL(k_emit, dim3(grid_rows), dim3(256), 0, s, w);
     const int bpp = (w.pool + 63) / 64;
-    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(64), (size_t)((w.pool + 1) & ~1) * sizeof(uint64_t), s, w, bpp);
+    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), s, w, bpp);
     return hipGetLastError();
 }
 

@@ -192,7 +192,14 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     mark(TR_STAGE_COMPAT);
     chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 8), s));
     mark(TR_STAGE_SC2);
-    chk(launch_sc2(w, grid_cap(h, (int64_t)B * nbs * (nbs + 1) / 2, 1), s));
+    {
+        // one workgroup per CU; the kernel splits its items into 8 equal ranges, one per XCD
+        // (workgroup g runs on XCD g mod 8), so the grid is a multiple of 8 with as many
+        // workgroups per XCD as its range holds items, up to the XCD's CUs
+        const int64_t items = (int64_t)B * nbs * (nbs + 1) / 2;
+        const int64_t per_xcd = std::min<int64_t>((items + 7) / 8, std::max(1, h->num_cus / 8));
+        chk(launch_sc2(w, (int)(8 * per_xcd), s));
+    }
     if (features_only) return e == hipSuccess ? TR_OK : TR_ERR_HIP;
     mark(TR_STAGE_PIVOTS);
     chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
@@ -315,7 +322,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->state, B));
     A(alloc(h, &h->plan, 1));
     A(alloc(h, &h->pre, (size_t)kNumPrefix * h->pre_stride));
-    A(alloc(h, &h->C, B * nn));
+    A(alloc(h, &h->C, B * nn / 2));   // packed E2M1, two entries per byte
     A(alloc(h, &h->G, B * nn));
     A(alloc(h, &h->ghist, B * kHistGroups * max_n));
     A(alloc(h, &h->rowmax, B * max_n));
@@ -467,8 +474,24 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
     const void *srcp = nullptr;
     size_t pitch = 0, width = 0, rows = 0;
     switch (tap) {
-    case TR_TAP_C:
-        need = n * n; srcp = h->C + d.c_off; pitch = d.npad; width = n; rows = n; break;
+    case TR_TAP_C: {   // stored as E2M1 nibbles (0x2 = 1): unpacked to one byte per entry here
+        need = n * n;
+        if (needed) *needed = need;
+        if (!host_dst) return TR_OK;
+        if (bytes < need) return TR_ERR_INVALID_ARG;
+        const size_t rb = (n + 1) / 2;
+        std::vector<uint8_t> packed(rb * n);
+        if (n && hipMemcpy2D(packed.data(), rb, h->C + d.c_off / 2, (size_t)d.npad / 2, rb, n,
+                             hipMemcpyDeviceToHost) != hipSuccess)
+            return TR_ERR_HIP;
+        uint8_t *o = static_cast<uint8_t *>(host_dst);
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j < n; ++j) {
+                const int nib = (packed[i * rb + j / 2] >> (4 * (j & 1))) & 0xF;
+                o[i * n + j] = nib == 0x2 ? 1 : (nib == 0 ? 0 : 0xFF);   // 0xFF: not a valid entry
+            }
+        return TR_OK;
+    }
     case TR_TAP_G:
         need = n * n * 2; srcp = h->G + d.g_off; pitch = (size_t)d.npad * 2; width = n * 2; rows = n; break;
     case TR_TAP_PIVOTS:
@@ -544,8 +567,9 @@ static const size_t kBlobBytes = 8 + TR_MLP_NPARAM * 4 + 8;
 
 tr_status tr_scorer_save(tr_handle *h, void *blob, size_t capacity, size_t *written)
 {
-    if (!h || !blob) return TR_ERR_INVALID_ARG;
+    if (!h) return TR_ERR_INVALID_ARG;
     if (written) *written = kBlobBytes;
+    if (!blob) return written ? TR_OK : TR_ERR_INVALID_ARG;   // size query
     if (capacity < kBlobBytes) return TR_ERR_INVALID_ARG;
     std::vector<float> w(TR_MLP_NPARAM);
     tr_status st = tr_scorer_get(h, w.data());

@@ -162,7 +162,7 @@ def tr_scorer_get(h):
 
 def tr_scorer_save(h) -> bytes:
     need = ct.c_size_t()
-    lib().tr_scorer_save(h, None, 0, ct.byref(need))
+    _ck(lib().tr_scorer_save(h, None, 0, ct.byref(need)), "tr_scorer_save")
     buf = ct.create_string_buffer(need.value)
     _ck(lib().tr_scorer_save(h, buf, need.value, ct.byref(need)), "tr_scorer_save")
     return buf.raw[:need.value]
