@@ -167,7 +167,10 @@ enum { TR_STAGE_PLAN = 0, TR_STAGE_COMPAT, TR_STAGE_SC2, TR_STAGE_PIVOTS, TR_STA
  * since the previous read (HIP events recorded on each call's stream, kept in
  * a ring so profiled calls never wait on the host). Synchronises those events
  * and resets the averages. TR_ERR_INVALID_ARG if no profiled call was made.
- * count <= TR_NUM_STAGES. */
+ * count <= TR_NUM_STAGES. The rigid fits run inside the clique kernel and the
+ * selection inside the scoring kernel, so TR_STAGE_CLIQUES includes the
+ * Kabsch fits, TR_STAGE_SCORE includes the selection, and the KABSCH and
+ * SELECT entries are zero. */
 tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count);
 
 const char *tr_status_string(int32_t status);

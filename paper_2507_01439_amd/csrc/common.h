@@ -10,11 +10,11 @@ namespace tr {
 constexpr int kSc2Tile = 256;     // output tile edge of the FP4 MFMA SC2 kernel; npad is a multiple
 constexpr int kHistGroups = 16;   // SC2 tiles add their weight histograms into this many copies per pair
 constexpr int kCompatTile = 64;   // tile edge of the compatibility kernel
-constexpr int kRowsPerItem = 16;  // rows per work item of the pivot scans
+constexpr int kRowsPerItem = 4;   // rows per work item of the pivot scans (one per wave)
 constexpr int kPrepRows = 256;    // rows per work item of the prep / feature kernels
 constexpr int kRankSortMax = 4096; // candidate lists up to this size are ordered by a rank sort
-constexpr int kScoreHyp = 256;    // hypotheses per scoring work item (one per thread)
-constexpr int kScorePts = 128;    // points per scoring work item
+constexpr int kScoreHyp = 64;     // hypotheses per scoring work item (four per thread)
+constexpr int kScorePts = 256;    // points per scoring work item (staged in LDS)
 
 // Work-list stages whose per-pair item counts depend on N_b; each has a
 // prefix array of B+1 entries in Plan::pre.
@@ -39,6 +39,10 @@ struct PairState {
     int32_t c_gt;       // edges heavier than alpha (all selected)
     int32_t m_eq;       // edges of weight alpha to take, in lexicographic order
     int32_t fallback;   // learned scores were not finite
+    int32_t fast;       // every pair of weight >= alpha fits the pivot pool: collected unordered, then sorted
+    int32_t ncand;      // keys the sort ranks (fast: c_gt + all ties; else K)
+    int32_t cand_cnt;   // keys collected so far (fast path)
+    int32_t done;       // workgroups of a fused stage that have finished this pair
 };
 
 struct Plan {
@@ -139,9 +143,7 @@ hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
 hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
 hipError_t launch_cliques(const Work &w, int B, hipStream_t s);
-hipError_t launch_kabsch(const Work &w, int B, hipStream_t s);
 hipError_t launch_score(const Work &w, int grid, hipStream_t s);
-hipError_t launch_select(const Work &w, int B, hipStream_t s);
 
 // Once per process and device, before any launch (and so outside stream capture):
 // raise the dynamic-LDS limits of the kernels that need more than 64 KiB.

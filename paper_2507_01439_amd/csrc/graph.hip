@@ -122,7 +122,8 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
         cnt[kCompat] = nb64 * (nb64 + 1) / 2;
         cnt[kSc2] = nbs * (nbs + 1) / 2;
         cnt[kRowBlk] = (nn + kRowsPerItem - 1) / kRowsPerItem;
-        cnt[kScore] = ok ? (int64_t)((H + kScoreHyp - 1) / kScoreHyp) * ((nn + kScorePts - 1) / kScorePts) : 0;
+        // an invalid pair still gets one (empty) scoring item: its last workgroup writes the result record
+        cnt[kScore] = ok ? (int64_t)((H + kScoreHyp - 1) / kScoreHyp) * ((nn + kScorePts - 1) / kScorePts) : (b < B);
         cnt[kNumPrefix] = (int64_t)npad * npad;   // arena bytes
         block_scan_multi<NV>(cnt, excl, tot, lds);
         if (b < B) {

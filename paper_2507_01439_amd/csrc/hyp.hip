@@ -6,112 +6,6 @@
 namespace tr {
 namespace {
 
-// ---------------------------------------------------------------- Eqs. 5-8
-
-// Candidate key: larger S first, then smaller z. Zero means "empty".
-__device__ __forceinline__ uint64_t clique_key(uint32_t S, uint32_t z)
-{
-    return ((uint64_t)S << 32) | (uint64_t)(0xFFFFFFFFu - z);
-}
-
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint64_t u = __shfl_xor(v, o, 64);
-        v = u > v ? u : v;
-    }
-    return v;
-}
-
-template <int KMAX>
-__device__ __forceinline__ void top_insert(uint64_t (&top)[KMAX], uint64_t k)
-{
-#pragma unroll
-    for (int s = 0; s < KMAX; ++s) {
-        const uint64_t t = top[s];
-        const bool gt = k > t;
-        top[s] = gt ? k : t;
-        k = gt ? t : k;
-    }
-}
-
-// One wavefront per pivot. On the O2Graph each lane reads eight consecutive
-// weights of rows i and j with one 16-byte load each (the wave covers 512
-// third vertices per step, z > j only); on the undirected graph lanes stride
-// over z and read the lower triangle through the transpose. Each lane keeps
-// its KMAX best keys sorted in registers (compare-and-swap insertion, no
-// dynamic register indexing); K2 rounds of a wave-wide max then pick the
-// pivot's cliques in (S desc, z asc) order.
-template <int KMAX>
-__global__ void __launch_bounds__(256) k_cliques(Work w, int total)
-{
-    const int lane = threadIdx.x & 63;
-    const int wave0 = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
-    for (int item = wave0; item < total; item += nwaves) {
-        const int b = item / w.k1, p = item - b * w.k1;
-        const PairDesc d = w.pairs[b];
-        const int32_t *pv = w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
-        const int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
-        int32_t *cl = w.cliques + (int64_t)b * w.h_cap * 3;
-        uint64_t top[KMAX];
-#pragma unroll
-        for (int s = 0; s < KMAX; ++s) top[s] = 0;
-        if (i >= 0) {
-            const uint16_t *G = w.G + d.g_off;
-            const int64_t npad = d.npad;
-            const int wij = i < j ? G[i * npad + j] : G[(int64_t)j * npad + i];
-            if (wij > 0 && w.graph == TR_GRAPH_O2) {
-                const uint16_t *ri = G + i * npad, *rj = G + (int64_t)j * npad;
-                const int c1 = (d.n + 7) >> 3;
-                // two chunks per lane in flight: 1024 third vertices per wave step
-                for (int c = ((j + 1) >> 3) + lane; c < c1; c += 128) {
-                    const bool two = c + 64 < c1;
-                    const uint4 qi = *reinterpret_cast<const uint4 *>(ri + 8 * c);
-                    const uint4 qj = *reinterpret_cast<const uint4 *>(rj + 8 * c);
-                    uint4 pi = make_uint4(0, 0, 0, 0), pj = make_uint4(0, 0, 0, 0);
-                    if (two) {
-                        pi = *reinterpret_cast<const uint4 *>(ri + 8 * (c + 64));
-                        pj = *reinterpret_cast<const uint4 *>(rj + 8 * (c + 64));
-                    }
-                    const uint32_t ui[8] = {qi.x, qi.y, qi.z, qi.w, pi.x, pi.y, pi.z, pi.w};
-                    const uint32_t uj[8] = {qj.x, qj.y, qj.z, qj.w, pj.x, pj.y, pj.z, pj.w};
-#pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int z = 8 * (c + (e >> 3) * 64) + (e & 7);
-                        const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                        const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                        if (z > j && z < d.n && giz > 0 && gjz > 0)
-                            top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
-                    }
-                }
-            } else if (wij > 0) {
-                for (int z = lane; z < d.n; z += 64) {
-                    if (z == i || z == j) continue;
-                    const int giz = i < z ? G[i * npad + z] : G[(int64_t)z * npad + i];
-                    const int gjz = j < z ? G[(int64_t)j * npad + z] : G[(int64_t)z * npad + j];
-                    if (giz > 0 && gjz > 0)
-                        top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
-                }
-            }
-        }
-        for (int s = 0; s < w.k2; ++s) {
-            const uint64_t best = wave_max_u64(top[0]);
-            if (best != 0 && top[0] == best) {          // keys are unique per z: one owner
-#pragma unroll
-                for (int q = 0; q + 1 < KMAX; ++q) top[q] = top[q + 1];
-                top[KMAX - 1] = 0;
-            }
-            if (lane == 0) {
-                const int64_t h = (int64_t)s * w.k1 + p;
-                cl[3 * h] = i;
-                cl[3 * h + 1] = j;
-                cl[3 * h + 2] = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)best) : -1;
-            }
-        }
-    }
-}
-
 // ---------------------------------------------------------------- Section 3.5
 
 // One Jacobi rotation of the symmetric 4x4 A (and the eigenvector matrix V)
@@ -178,21 +72,17 @@ __device__ __forceinline__ void adj_col(const double (&A)[4][4], double (&v)[4])
 // eigenvector is the largest column of adj(K - lambda I). When that column
 // vanishes (a repeated top eigenvalue: collinear or coincident points) the
 // cyclic Jacobi method on K decides instead. float64 throughout, then R and t
-// are rounded to float32. One thread per hypothesis; IN is initialised here.
-__global__ void __launch_bounds__(256) k_kabsch(Work w, int total)
+// are rounded to float32. IN is initialised here (0, or -1 for an empty clique).
+__device__ void fit_pose(const Work &w, const PairDesc &d, int64_t slot, int ia, int ib, int ic)
 {
-    for (int item = blockIdx.x * blockDim.x + threadIdx.x; item < total; item += gridDim.x * blockDim.x) {
-        const int b = item / w.H, h = item - b * w.H;
-        const PairDesc d = w.pairs[b];
-        const int32_t *c = w.cliques + ((int64_t)b * w.h_cap + h) * 3;
-        float *pose = w.poses + ((int64_t)b * w.h_cap + h) * 12;
-        int32_t *inl = w.inl + (int64_t)b * w.h_cap + h;
-        const int ia = c[0], ib = c[1], ic = c[2];
+    {
+        float *pose = w.poses + slot * 12;
+        int32_t *inl = w.inl + slot;
         if (d.n == 0 || ic < 0) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) pose[k] = (k < 9 && k % 4 == 0) ? 1.0f : 0.0f;
             *inl = -1;
-            continue;
+            return;
         }
         const int idx[3] = {ia, ib, ic};
         double P[3][3], Q[3][3], pb[3] = {0, 0, 0}, qb[3] = {0, 0, 0};
@@ -316,6 +206,117 @@ __global__ void __launch_bounds__(256) k_kabsch(Work w, int total)
     }
 }
 
+// ---------------------------------------------------------------- Eqs. 5-8
+
+// Candidate key: larger S first, then smaller z. Zero means "empty".
+__device__ __forceinline__ uint64_t clique_key(uint32_t S, uint32_t z)
+{
+    return ((uint64_t)S << 32) | (uint64_t)(0xFFFFFFFFu - z);
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+template <int KMAX>
+__device__ __forceinline__ void top_insert(uint64_t (&top)[KMAX], uint64_t k)
+{
+#pragma unroll
+    for (int s = 0; s < KMAX; ++s) {
+        const uint64_t t = top[s];
+        const bool gt = k > t;
+        top[s] = gt ? k : t;
+        k = gt ? t : k;
+    }
+}
+
+// One wavefront per pivot. On the O2Graph each lane reads eight consecutive
+// weights of rows i and j with one 16-byte load each (the wave covers 512
+// third vertices per step, z > j only); on the undirected graph lanes stride
+// over z and read the lower triangle through the transpose. Each lane keeps
+// its KMAX best keys sorted in registers (compare-and-swap insertion, no
+// dynamic register indexing); K2 rounds of a wave-wide max then pick the
+// pivot's cliques in (S desc, z asc) order.
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_cliques(Work w, int total)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave0 = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
+    for (int item = wave0; item < total; item += nwaves) {
+        const int b = item / w.k1, p = item - b * w.k1;
+        const PairDesc d = w.pairs[b];
+        const int32_t *pv = w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
+        const int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
+        int32_t *cl = w.cliques + (int64_t)b * w.h_cap * 3;
+        uint64_t top[KMAX];
+#pragma unroll
+        for (int s = 0; s < KMAX; ++s) top[s] = 0;
+        if (i >= 0) {
+            const uint16_t *G = w.G + d.g_off;
+            const int64_t npad = d.npad;
+            const int wij = i < j ? G[i * npad + j] : G[(int64_t)j * npad + i];
+            if (wij > 0 && w.graph == TR_GRAPH_O2) {
+                const uint16_t *ri = G + i * npad, *rj = G + (int64_t)j * npad;
+                const int c1 = (d.n + 7) >> 3;
+                // two chunks per lane in flight: 1024 third vertices per wave step
+                for (int c = ((j + 1) >> 3) + lane; c < c1; c += 128) {
+                    const bool two = c + 64 < c1;
+                    const uint4 qi = *reinterpret_cast<const uint4 *>(ri + 8 * c);
+                    const uint4 qj = *reinterpret_cast<const uint4 *>(rj + 8 * c);
+                    uint4 pi = make_uint4(0, 0, 0, 0), pj = make_uint4(0, 0, 0, 0);
+                    if (two) {
+                        pi = *reinterpret_cast<const uint4 *>(ri + 8 * (c + 64));
+                        pj = *reinterpret_cast<const uint4 *>(rj + 8 * (c + 64));
+                    }
+                    const uint32_t ui[8] = {qi.x, qi.y, qi.z, qi.w, pi.x, pi.y, pi.z, pi.w};
+                    const uint32_t uj[8] = {qj.x, qj.y, qj.z, qj.w, pj.x, pj.y, pj.z, pj.w};
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int z = 8 * (c + (e >> 3) * 64) + (e & 7);
+                        const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                        const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                        if (z > j && z < d.n && giz > 0 && gjz > 0)
+                            top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
+                    }
+                }
+            } else if (wij > 0) {
+                for (int z = lane; z < d.n; z += 64) {
+                    if (z == i || z == j) continue;
+                    const int giz = i < z ? G[i * npad + z] : G[(int64_t)z * npad + i];
+                    const int gjz = j < z ? G[(int64_t)j * npad + z] : G[(int64_t)z * npad + j];
+                    if (giz > 0 && gjz > 0)
+                        top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
+                }
+            }
+        }
+        int zmine = -1;   // lane s < K2 keeps the third vertex of clique s
+        for (int s = 0; s < w.k2; ++s) {
+            const uint64_t best = wave_max_u64(top[0]);
+            if (best != 0 && top[0] == best) {          // keys are unique per z: one owner
+#pragma unroll
+                for (int q = 0; q + 1 < KMAX; ++q) top[q] = top[q + 1];
+                top[KMAX - 1] = 0;
+            }
+            const int z = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)best) : -1;
+            if (lane == s) zmine = z;
+            if (lane == 0) {
+                const int64_t h = (int64_t)s * w.k1 + p;
+                cl[3 * h] = i;
+                cl[3 * h + 1] = j;
+                cl[3 * h + 2] = z;
+            }
+        }
+        // one rigid fit per clique (Section 3.5), on lanes 0..K2-1
+        if (lane < w.k2) fit_pose(w, d, (int64_t)b * w.h_cap + (int64_t)lane * w.k1 + p, i, j, zmine);
+    }
+}
+
 // ---------------------------------------------------------------- Eq. 9
 
 // Residual |R x + t - y|^2 in float32 with the pinned operation order: each
@@ -345,73 +346,33 @@ __device__ __forceinline__ float residual2(const float (&ps)[12], float x0, floa
     return s;
 }
 
-__device__ __forceinline__ float lane_bcast(float v, int q)
+// Inclusive prefix sum inside each 16-lane DPP row: the last lane of a row (16r + 15) holds its total.
+__device__ __forceinline__ int row16_scan(int v)
 {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    return v;
 }
 
-// Work item = 256 hypotheses x kScorePts matches of one pair. Each thread
-// holds one pose in registers. The matches are the same for the whole wave:
-// each lane loads one of 64 (coalesced), and v_readlane hands every match to
-// all lanes as scalar operands, so the inner loop touches neither LDS nor
-// memory. Partial counts go to IN with one integer atomic per thread, so the
-// result does not depend on the order.
-__global__ void __launch_bounds__(256) k_score(Work w)
+// The pair's result once every hypothesis is scored: argmax of IN (lowest h
+// on ties), the compatibility counts summed over the pair's tiles, the result
+// record and the inlier mask under the selected pose. Run by one 256-thread
+// workgroup.
+__device__ void select_pair(const Work &w, int b)
 {
-    const int total = w.plan->total[kScore], B = w.plan->B;
-    const int32_t *pre = w.pre + kScore * w.pre_stride;
-    const float th2 = w.theta * w.theta;
-    const int lane = threadIdx.x & 63;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
-        const int npc = (d.n + kScorePts - 1) / kScorePts;
-        const int local = item - pre[b], hb = local / npc, pc = local - hb * npc;
-        const int k0 = pc * kScorePts, cnt = min(kScorePts, d.n - k0);
-        const int h = hb * kScoreHyp + threadIdx.x;
-        int32_t *inl = w.inl + (int64_t)b * w.h_cap + h;
-        const bool live = h < w.H && *inl >= 0;
-        if (!__any(live)) continue;
-        float ps[12];
-        const float *pose = w.poses + ((int64_t)b * w.h_cap + min(h, w.H - 1)) * 12;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) ps[k] = pose[k];
-        int c = 0;
-        for (int kb = 0; kb < cnt; kb += 64) {
-            const int kk = kb + lane;
-            float m[6] = {0, 0, 0, 0, 0, 0};
-            if (kk < cnt) {
-                const int64_t g = d.pt_off + k0 + kk;
-#pragma unroll
-                for (int f = 0; f < 3; ++f) { m[f] = w.src[3 * g + f]; m[3 + f] = w.dst[3 * g + f]; }
-            }
-            const int mcount = min(64, cnt - kb);
-            for (int q = 0; q < mcount; ++q)
-                c += residual2(ps, lane_bcast(m[0], q), lane_bcast(m[1], q), lane_bcast(m[2], q),
-                               lane_bcast(m[3], q), lane_bcast(m[4], q), lane_bcast(m[5], q)) <= th2;
-        }
-        if (live && c) atomicAdd(inl, c);
-    }
-}
-
-// ---------------------------------------------------------------- selection
-
-// One workgroup per pair: argmax of IN (lowest h on ties), the compatibility
-// counts summed over the pair's tiles, the result record and the inlier mask
-// under the selected pose.
-__global__ void __launch_bounds__(1024) k_select(Work w)
-{
-    __shared__ uint64_t red[16];
-    __shared__ int32_t cnt[16][3];
-    const int b = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ uint64_t red[4];
+    __shared__ int32_t cnt[4][3];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const PairDesc d = w.pairs[b];
     const PairState st = w.state[b];
     uint64_t best = 0;
     int nvalid = 0, nbnd = 0, nedge = 0;
     if (d.n > 0) {
         const int32_t *inl = w.inl + (int64_t)b * w.h_cap;
-        for (int h = threadIdx.x; h < w.H; h += 1024) {
-            const int v = inl[h];
+        for (int h = tid; h < w.H; h += 256) {
+            const int v = __atomic_load_n(&inl[h], __ATOMIC_RELAXED);   // written by other workgroups
             if (v >= 0) {
                 ++nvalid;
                 const uint64_t k = ((uint64_t)(v + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
@@ -419,7 +380,7 @@ __global__ void __launch_bounds__(1024) k_select(Work w)
             }
         }
         const int32_t *pre = w.pre + kCompat * w.pre_stride;
-        for (int t = pre[b] + threadIdx.x; t < pre[b + 1]; t += 1024) {
+        for (int t = pre[b] + tid; t < pre[b + 1]; t += 256) {
             nbnd += w.cnt_part[2 * (int64_t)t];
             nedge += w.cnt_part[2 * (int64_t)t + 1];
         }
@@ -435,7 +396,7 @@ __global__ void __launch_bounds__(1024) k_select(Work w)
     __syncthreads();
     best = 0;
     nvalid = nbnd = nedge = 0;
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < 4; ++k) {
         best = red[k] > best ? red[k] : best;
         nvalid += cnt[k][0];
         nbnd += cnt[k][1];
@@ -451,7 +412,7 @@ __global__ void __launch_bounds__(1024) k_select(Work w)
 #pragma unroll
         for (int k = 0; k < 12; ++k) ps[k] = (k < 9 && k % 4 == 0) ? 1.0f : 0.0f;
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         tr_result r;
         for (int k = 0; k < 9; ++k) r.R[k] = ps[k];
         for (int k = 0; k < 3; ++k) r.t[k] = ps[9 + k];
@@ -472,12 +433,79 @@ __global__ void __launch_bounds__(1024) k_select(Work w)
     }
     if (w.masks && d.n > 0) {
         const float th2 = w.theta * w.theta;
-        for (int k = threadIdx.x; k < d.n; k += 1024) {
+        for (int k = tid; k < d.n; k += 256) {
             const int64_t g = d.pt_off + k;
             const bool in = hbest >= 0 && residual2(ps, w.src[3 * g], w.src[3 * g + 1], w.src[3 * g + 2], w.dst[3 * g],
                                                     w.dst[3 * g + 1], w.dst[3 * g + 2]) <= th2;
             w.masks[g] = in ? 1 : 0;
         }
+    }
+}
+
+// Work item = kScoreHyp (64) hypotheses x kScorePts (256) matches of one
+// pair. The matches are staged in LDS; thread (q, l) holds the four poses
+// 4q .. 4q+3 in registers and scores them on matches l, l+16, ..., so every
+// LDS read serves four residuals. The 16 partial counts of a pose (one DPP
+// row) are summed in registers and added to IN with one integer atomic, so
+// the result does not depend on the order. The workgroup that finishes the
+// last item of a pair (atomic ticket, no waiting) then selects the pair's
+// result.
+__global__ void __launch_bounds__(256) k_score(Work w)
+{
+    __shared__ float4 pts[kScorePts][2];
+    __shared__ int32_t last;
+    const int total = w.plan->total[kScore], B = w.plan->B;
+    const int32_t *pre = w.pre + kScore * w.pre_stride;
+    const float th2 = w.theta * w.theta;
+    const int tid = threadIdx.x, q = tid >> 4, l = tid & 15;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = find_pair(pre, B, item);
+        const PairDesc d = w.pairs[b];
+        const int npc = max(1, (d.n + kScorePts - 1) / kScorePts);
+        const int local = item - pre[b], hb = local / npc, pc = local - hb * npc;
+        const int k0 = pc * kScorePts, cnt = max(0, min(kScorePts, d.n - k0));
+        if (tid < cnt) {
+            const int64_t g = d.pt_off + k0 + tid;
+            pts[tid][0] = make_float4(w.src[3 * g], w.src[3 * g + 1], w.src[3 * g + 2], 0.0f);
+            pts[tid][1] = make_float4(w.dst[3 * g], w.dst[3 * g + 1], w.dst[3 * g + 2], 0.0f);
+        }
+        float ps[4][12];
+        bool live[4];
+        int32_t *inl = w.inl + (int64_t)b * w.h_cap;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int h = hb * kScoreHyp + 4 * q + u;
+            live[u] = h < w.H && inl[h] >= 0;
+            const float *pose = w.poses + ((int64_t)b * w.h_cap + min(h, w.H - 1)) * 12;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) ps[u][k] = pose[k];
+        }
+        __syncthreads();
+        int c[4] = {0, 0, 0, 0};
+        for (int k = l; k < cnt; k += 16) {
+            const float4 x = pts[k][0], y = pts[k][1];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] += residual2(ps[u], x.x, x.y, x.z, y.x, y.y, y.z) <= th2;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = row16_scan(c[u]);
+            if (l == 15 && live[u] && c[u]) atomicAdd(&inl[hb * kScoreHyp + 4 * q + u], c[u]);
+        }
+        // Device-scope integer atomics are performed at the device's coherence point, so once every
+        // thread has seen its own additions acknowledged (vmcnt 0) and the workgroup has met, the
+        // ticket below is ordered after all of them; the last workgroup reads IN with cache-bypassing
+        // atomic loads. (A full __threadfence here would write back and invalidate the XCD's L2 on
+        // every item.)
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            const int t = atomicAdd(&w.state[b].done, 1);
+            last = t == pre[b + 1] - pre[b] - 1;
+        }
+        __syncthreads();
+        if (last) select_pair(w, b);
+        __syncthreads();   // pts and last are the next item's
     }
 }
 
@@ -492,23 +520,9 @@ hipError_t launch_cliques(const Work &w, int B, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_kabsch(const Work &w, int B, hipStream_t s)
-{
-    const int total = B * w.H;
-    const int grid = min((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_kabsch, dim3(grid), dim3(256), 0, s, w, total);
-    return hipGetLastError();
-}
-
 hipError_t launch_score(const Work &w, int grid, hipStream_t s)
 {
     hipLaunchKernelGGL(k_score, dim3(grid), dim3(256), 0, s, w);
-    return hipGetLastError();
-}
-
-hipError_t launch_select(const Work &w, int B, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_select, dim3(B), dim3(1024), 0, s, w);
     return hipGetLastError();
 }
 

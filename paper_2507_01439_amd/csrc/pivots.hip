@@ -10,12 +10,15 @@
 //   per-row maximum of the upper triangle)
 //   k_thresh   sums the histograms; finds alpha, the pairs heavier than it
 //              (c_gt) and the ties to take (m)
-//   k_rowcount per row: pairs > alpha and == alpha (rows whose maximum is
-//              below alpha are not read); per row block: their sums
+//   k_rowscan  fast path: collects every pair of weight >= alpha (when they
+//              fit the pool) for the sort; ordered path: per row, pairs
+//              > alpha and == alpha; per row block, their sums
 //   k_emit     every row writes its keys at its own offset, in row-major order:
 //              the > alpha keys first, then the first m ties (already in order)
-//   k_sort     orders the K keys by (w desc, i asc, j asc)
-// No output position depends on atomics, so the pivot list is deterministic.
+//   k_sort     ranks the collected keys by (w desc, i asc, j asc) and keeps
+//              the first K
+// The key set is exact on both paths and the sort decides every position, so
+// the pivot list does not depend on the order atomics were served in.
 #include "common.h"
 
 namespace tr {
@@ -139,11 +142,20 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     const int64_t K = d.kpiv;
     if (K <= 0) return;
     const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.max_n;
-    for (int v = threadIdx.x; v < d.n; v += 1024) {
-        int32_t c = 0;
+    // the 16 copies of four bins per thread are loaded before any is summed (the pass is latency-bound)
+    for (int v0 = threadIdx.x; v0 < d.n; v0 += 4096) {
+        int32_t c[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int g = 0; g < kHistGroups; ++g) c += gh[(int64_t)g * w.max_n + v];
-        hs[v] = c;
+        for (int u = 0; u < 4; ++u) {
+            const int v = v0 + 1024 * u;
+            if (v < d.n) {
+#pragma unroll
+                for (int g = 0; g < kHistGroups; ++g) c[u] += gh[(int64_t)g * w.max_n + v];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (v0 + 1024 * u < d.n) hs[v0 + 1024 * u] = c[u];
     }
     __syncthreads();
     const int nb = d.n - 1;                     // bins w = 1 .. n-1, walked from the top
@@ -165,75 +177,153 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        w.state[b].alpha = res[0];
-        w.state[b].c_gt = res[1];
+        const int alpha = res[0], c_gt = res[1];
+        // pairs of weight alpha: the histogram bin, or every pair of weight 0
+        const int64_t ties = alpha > 0 ? hs[alpha] : (int64_t)d.n * (d.n - 1) / 2 - tot;
+        const bool fast = c_gt + ties <= w.pool_cap;
+        w.state[b].alpha = alpha;
+        w.state[b].c_gt = c_gt;
         w.state[b].m_eq = res[2];
+        w.state[b].fast = fast ? 1 : 0;
+        w.state[b].ncand = fast ? (int32_t)(c_gt + ties) : (int32_t)K;
     }
 }
 
-// ---------------------------------------------------------------- ordered emission
+// ---------------------------------------------------------------- row scan
 
-// Per row: pairs heavier than alpha and pairs equal to alpha; per block: their sums.
-__global__ void __launch_bounds__(256) k_rowcount(Work w)
+constexpr int kCollectCap = 2048;   // keys a workgroup stages in LDS before its one global reservation
+
+// One row (i, j > i) of the O2Graph per wave, all of its 16-byte chunks of
+// weights loaded before any is used (the pass is latency-bound); rows whose
+// maximum is below alpha are not read.
+//
+// Fast path (every pair of weight >= alpha fits the pool): the pairs of
+// weight >= alpha are appended to the pool in no particular order; their
+// count is exactly c_gt + (pairs of weight alpha), and the rank sort fixes the
+// order. A workgroup stages its keys in LDS, reserves its range of the pool
+// with one atomic and copies them out; if its rows hold more than
+// kCollectCap keys it reserves the count first and writes straight to the
+// pool on a second read of those rows.
+//
+// Ordered path: per row, the pairs heavier than alpha and equal to it and a
+// mask of the 512-column segments holding any of them; per row block, their
+// sums (the emission kernel then writes every key at its final position).
+__global__ void __launch_bounds__(256) k_rowscan(Work w)
 {
+    __shared__ uint64_t buf[kCollectCap];
+    __shared__ int32_t nbuf, base;
     __shared__ int32_t part[4][2];
     const int total = w.plan->total[kRowBlk], B = w.plan->B;
     const int32_t *pre = w.pre + kRowBlk * w.pre_stride;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int b = find_pair(pre, B, item);
+        const PairState st = w.state[b];
         const PairDesc d = w.pairs[b];
-        const int alpha = w.state[b].alpha;
-        const int blk = item - pre[b];
-        const int c1 = (d.n + 7) >> 3;
-        int sg = 0, se = 0;
-        // a row whose largest weight is below alpha holds no candidate (alpha = 0: every row does)
-        const int myrow = blk * kRowsPerItem + (lane & (kRowsPerItem - 1));
-        const int rmax = (myrow < d.n) ? w.rowmax[(int64_t)b * w.max_n + myrow] : 0;
-        for (int rr = 0; rr < kRowsPerItem / 4; ++rr) {
-            const int i = blk * kRowsPerItem + wv * (kRowsPerItem / 4) + rr;
-            if (i >= d.n) break;
-            const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
-            const int rm = __builtin_amdgcn_readlane(rmax, wv * (kRowsPerItem / 4) + rr);
-            const int c_lo = (i + 1) >> 3;
-            const int cstart = (alpha > 0 && rm < alpha) ? c1 : c_lo;
-            int cnt = 0;
-            uint64_t segs = 0;
-            // segments of 64 chunks (512 columns), eight 16-byte loads in flight per lane
-            for (int c0 = cstart; c0 < c1; c0 += 512) {
-                uint4 q[8];
+        if (d.kpiv <= 0) continue;   // same for the whole workgroup
+        const int blk = item - pre[b], alpha = st.alpha, c1 = (d.n + 7) >> 3;
+        const int i = blk * kRowsPerItem + wv;
+        const int rm = i < d.n ? w.rowmax[(int64_t)b * w.max_n + i] : 0;
+        const bool live = i < d.n && !(alpha > 0 && rm < alpha);
+        const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
+        const int c_lo = (i + 1) >> 3;
+        uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
+        // mode 0: count (ordered path); 1: stage into buf; 2: write cand[base + ...]
+        auto scan = [&](int mode, int &cnt, uint64_t &segs) {
+            cnt = 0;
+            segs = 0;
+            for (int c0 = c_lo; c0 < c1; c0 += 1024) {
+                uint4 q[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const int c = c0 + 64 * u + lane;
                     q[u] = c < c1 ? *reinterpret_cast<const uint4 *>(row + 8 * c) : make_uint4(0, 0, 0, 0);
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < 16; ++u) {
                     const int c = c0 + 64 * u + lane;
-                    bool hit = false;
-                    if (c < c1) cnt += chunk_counts(q[u], c, i, d.n, alpha, hit);
-                    if (__any(hit)) segs |= 1ull << ((c0 - c_lo) / 64 + u);   // at most 64 segments (N < 32768)
+                    if (mode == 0) {
+                        bool hit = false;
+                        if (c < c1) cnt += chunk_counts(q[u], c, i, d.n, alpha, hit);
+                        if (__any(hit)) segs |= 1ull << ((c0 - c_lo) / 64 + u);   // at most 64 segments (N < 32768)
+                        continue;
+                    }
+                    const uint32_t uw[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+                    int m = 0;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int j = 8 * c + e, v = (int)((uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                        m += (c < c1 && j > i && j < d.n && v >= alpha);
+                    }
+                    const int incl = wave_incl_scan(m);
+                    const int tot = __builtin_amdgcn_readlane(incl, 63);
+                    if (tot == 0) continue;
+                    int off = 0;
+                    if (lane == 63) off = atomicAdd(&nbuf, tot);
+                    off = __builtin_amdgcn_readlane(off, 63) + incl - m;
+                    if (m) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int j = 8 * c + e, v = (int)((uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                            if (j > i && j < d.n && v >= alpha) {
+                                if (mode == 2) {
+                                    if (base + off < w.pool_cap) cand[base + off] = pivot_key(v, i, j);
+                                } else if (off < kCollectCap) {
+                                    buf[off] = pivot_key(v, i, j);
+                                }
+                                ++off;
+                            }
+                        }
+                    }
                 }
             }
+        };
+        int cnt;
+        uint64_t segs;
+        if (st.fast) {
+            if (tid == 0) nbuf = 0;
+            __syncthreads();
+            if (live) scan(1, cnt, segs);
+            __syncthreads();
+            const int n_wg = nbuf;
+            __syncthreads();   // every thread has read nbuf before it is reset
+            if (n_wg == 0) continue;
+            if (tid == 0) base = atomicAdd(&w.state[b].cand_cnt, n_wg);
+            __syncthreads();
+            if (n_wg <= kCollectCap) {
+                for (int k = tid; k < n_wg; k += 256)
+                    if (base + k < w.pool_cap) cand[base + k] = buf[k];
+            } else {
+                if (tid == 0) nbuf = 0;
+                __syncthreads();
+                if (live) scan(2, cnt, segs);
+            }
+            __syncthreads();   // buf, nbuf and base are the next item's
+        } else {
+            cnt = 0;
+            segs = 0;
+            if (live) scan(0, cnt, segs);
             cnt = __builtin_amdgcn_readlane(wave_incl_scan(cnt), 63);
             const int cg = cnt & 0xFFFF, ce = cnt >> 16;
             if (lane == 0) {
-                w.rowcnt[((int64_t)b * w.max_n + i) * 2] = cg;
-                w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] = ce;
-                w.rowseg[(int64_t)b * w.max_n + i] = segs;
+                if (i < d.n) {
+                    w.rowcnt[((int64_t)b * w.max_n + i) * 2] = cg;
+                    w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] = ce;
+                    w.rowseg[(int64_t)b * w.max_n + i] = segs;
+                }
+                part[wv][0] = cg;
+                part[wv][1] = ce;
             }
-            sg += cg;
-            se += ce;
+            __syncthreads();
+            if (tid < 2)
+                w.blkcnt[((int64_t)b * w.nblk_stride + blk) * 2 + tid] = part[0][tid] + part[1][tid] + part[2][tid] +
+                                                                          part[3][tid];
+            __syncthreads();
         }
-        if (lane == 0) { part[wv][0] = sg; part[wv][1] = se; }
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            int s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] + part[3][threadIdx.x];
-            w.blkcnt[((int64_t)b * w.nblk_stride + blk) * 2 + threadIdx.x] = s;
-        }
-        __syncthreads();
     }
 }
+
+// ---------------------------------------------------------------- ordered emission
 
 // Write every pivot's key at its final rank among (> alpha) or (== alpha) pairs.
 __global__ void __launch_bounds__(256) k_emit(Work w)
@@ -247,6 +337,7 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
         const int b = find_pair(pre, B, item);
         const PairState st = w.state[b];
         const PairDesc d = w.pairs[b];
+        if (st.fast || d.kpiv <= 0) continue;   // same for the whole workgroup
         const int blk = item - pre[b];
         // counts of all earlier blocks of this pair
         int64_t pg = 0, pe = 0;
@@ -345,14 +436,15 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = w.pairs[b];
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int NC = K > 0 ? min(w.state[b].ncand, w.pool_cap) : 0;   // keys ranked; the first K are kept
     int32_t *out = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
-    if (g * 64 >= max(K, w.pool)) return;
+    if (g * 64 >= max(NC, w.pool)) return;
     const uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
-    const int K16 = (K + 15) & ~15;   // padded with keys larger than any real one
-    for (int k = tid; k < K16; k += 256) keys[k] = k < K ? cand[k] : ~0ull;
+    const int K16 = (NC + 15) & ~15;   // padded with keys larger than any real one
+    for (int k = tid; k < K16; k += 256) keys[k] = k < NC ? cand[k] : ~0ull;
     __syncthreads();
     const int p = g * 64 + lane;
-    const uint64_t mine = p < K ? keys[p] : 0;
+    const uint64_t mine = p < NC ? keys[p] : 0;
     const int per = ((K16 / 16 + 3) / 4) * 16;
     const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
     int r = 0;
@@ -369,12 +461,13 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     part[wv][lane] = r;
     __syncthreads();
     if (wv != 0) return;
-    if (p < K) {
-        const int rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    const int rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    if (p < NC && rk < K) {
         out[3 * rk] = (int32_t)((mine >> 20) & 0xFFFFF);
         out[3 * rk + 1] = (int32_t)(mine & 0xFFFFF);
         out[3 * rk + 2] = (int32_t)(0xFFFFu - (uint32_t)(mine >> 40));
-    } else if (p < w.pool) {
+    }
+    if (p >= K && p < w.pool) {   // slots past the pair's pivots
         out[3 * p] = -1;
         out[3 * p + 1] = -1;
         out[3 * p + 2] = 0;
@@ -386,10 +479,11 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s)
 {
     hipLaunchKernelGGL(k_thresh, dim3(B), dim3(1024), (size_t)w.max_n * sizeof(int32_t), s, w);
-    hipLaunchKernelGGL(k_rowcount, dim3(grid_rows), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_rowscan, dim3(grid_rows), dim3(256), 0, s, w);
     hipLaunchKernelGGL(k_emit, dim3(grid_rows), dim3(256), 0, s, w);
-    const int bpp = (w.pool + 63) / 64;
-    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), s, w, bpp);
+    const int bpp = (w.pool_cap + 63) / 64;   // the fast path may rank up to pool_cap keys
+    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(256), (size_t)((w.pool_cap + 15) & ~15) * sizeof(uint64_t), s, w,
+                       bpp);
     return hipGetLastError();
 }
 

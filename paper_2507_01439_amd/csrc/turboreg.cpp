@@ -210,14 +210,12 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
         chk(launch_learned_order(w, h->mlp, B, g, s));
     }
     mark(TR_STAGE_CLIQUES);
-    chk(launch_cliques(w, B, s));
+    chk(launch_cliques(w, B, s));   // also fits each clique's pose (the Kabsch stage)
     mark(TR_STAGE_KABSCH);
-    chk(launch_kabsch(w, B, s));
     mark(TR_STAGE_SCORE);
     const int64_t score_items = (int64_t)B * ((w.H + kScoreHyp - 1) / kScoreHyp) * ((max_n + kScorePts - 1) / kScorePts);
-    chk(launch_score(w, grid_cap(h, score_items, 8), s));
+    chk(launch_score(w, grid_cap(h, score_items, 8), s));   // its last workgroup per pair selects the result
     mark(TR_STAGE_SELECT);
-    chk(launch_select(w, B, s));
     mark(TR_NUM_STAGES);
     if (e != hipSuccess) {
         std::fprintf(stderr, "turboreg: launch failed: %s\n", hipGetErrorString(e));

@@ -96,6 +96,17 @@ def test_heavy_ties_noiseless_clique(reg):
     assert r.best_inliers == 200
 
 
+def test_fast_collection_past_stage_capacity(reg):
+    # noiseless full clique: every pair ties at alpha = N - 2 and all 15753 pairs fit the pool, so they are
+    # collected unordered; rows 0..15 alone hold 2712 of them (more than one workgroup stages in LDS)
+    p = indoor(178, 1.0, 16, sigma=0.0)
+    prm = T.make_params(0.01, 0.01, k1=2000, k2=2)
+    say("fast collection, 2712 keys in the first row block")
+    r, mask = run_single(reg, torch, p.src, p.dst, prm)
+    check_taps(reg, p.src, p.dst, prm, r, mask, label="collect overflow")
+    assert r.n_pivots == 2000
+
+
 def test_all_outliers_no_hypothesis(reg):
     p = indoor(300, 0.0, 11)
     prm = T.make_params(1e-4, 0.1, k1=50, k2=2)
