@@ -49,7 +49,11 @@ typedef enum {
 
 enum { TR_GRAPH_O2 = 0, TR_GRAPH_SC2 = 1 };          /* Definition 2 / undirected SC2 graph */
 enum { TR_PIVOTS_PLAIN = 0, TR_PIVOTS_LEARNED = 1 };
-enum { TR_FLAG_PROFILE = 1u };  /* record per-stage HIP events; read with tr_stage_times */
+enum {
+    TR_FLAG_PROFILE = 1u,       /* record per-stage HIP events; read with tr_stage_times          */
+    TR_FLAG_PROFILE_SC2 = 2u    /* record only the two events around the SC2 kernel (its launch  */
+                                /* duration, least perturbation); ignored with TR_FLAG_PROFILE   */
+};
 
 typedef struct {
     float tau;            /* compatibility threshold, metres; Eq. 1 uses "<="                    */
@@ -164,7 +168,8 @@ enum { TR_STAGE_PLAN = 0, TR_STAGE_COMPAT, TR_STAGE_SC2, TR_STAGE_PIVOTS, TR_STA
        TR_STAGE_CLIQUES, TR_STAGE_KABSCH, TR_STAGE_SCORE, TR_STAGE_SELECT, TR_NUM_STAGES };
 
 /* Average milliseconds per stage over the calls made with TR_FLAG_PROFILE
- * since the previous read (HIP events recorded on each call's stream, kept in
+ * (every stage) or TR_FLAG_PROFILE_SC2 (the SC2 stage only; 0 elsewhere unless
+ * other calls recorded them) since the previous read (HIP events recorded on each call's stream, kept in
  * a ring so profiled calls never wait on the host). Synchronises those events
  * and resets the averages. TR_ERR_INVALID_ARG if no profiled call was made.
  * count <= TR_NUM_STAGES. The rigid fits run inside the clique kernel and the

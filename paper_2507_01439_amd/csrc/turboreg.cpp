@@ -64,10 +64,10 @@ struct tr_handle {
     // stalling the stream; per-stage sums over the calls since the last read
     static constexpr int kRing = 256;
     std::vector<hipEvent_t> ring;          // kRing x (TR_NUM_STAGES + 1)
-    std::vector<char> ring_pending;
+    std::vector<char> ring_pending;        // 0 free, 1 all stages recorded, 2 only the SC2 stage
     int64_t ring_next = 0;
     double stage_sum[TR_NUM_STAGES] = {};
-    int64_t stage_calls = 0;
+    int64_t stage_calls[TR_NUM_STAGES] = {};
     // captured batches
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     std::vector<void *> allocs;
@@ -173,14 +173,14 @@ tr_status check_params(tr_handle *h, const tr_params *p)
 // The launch sequence for B pairs (offsets on the device) or one pair (n_single).
 // features_only stops after the learned features.
 tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n_single, int32_t B,
-                  int32_t max_n, hipEvent_t *ev, bool features_only, hipStream_t s)
+                  int32_t max_n, hipEvent_t *ev, int ev_mode, bool features_only, hipStream_t s)
 {
     const bool profile = ev != nullptr;
     const int64_t npad = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
     const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
     const int64_t rows_items = (int64_t)B * ((max_n + kRowsPerItem - 1) / kRowsPerItem);
     auto mark = [&](int stage) {
-        if (profile) hipEventRecord(ev[stage], s);
+        if (profile && (ev_mode == 1 || stage == TR_STAGE_SC2 || stage == TR_STAGE_SC2 + 1)) hipEventRecord(ev[stage], s);
     };
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -236,21 +236,29 @@ void remember(tr_handle *h, const Work &w, int32_t B, hipStream_t s)
 hipError_t ring_collect(tr_handle *h, int slot)
 {
     hipEvent_t *ev = &h->ring[(size_t)slot * (TR_NUM_STAGES + 1)];
-    hipError_t e = hipEventSynchronize(ev[TR_NUM_STAGES]);
+    const bool all = h->ring_pending[slot] == 1;
+    hipError_t e = hipEventSynchronize(ev[all ? TR_NUM_STAGES : TR_STAGE_SC2 + 1]);
     if (e != hipSuccess) return e;
     for (int k = 0; k < TR_NUM_STAGES; ++k) {
+        if (!all && k != TR_STAGE_SC2) continue;
         float t = 0;
         e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
         if (e != hipSuccess) return e;
         h->stage_sum[k] += t;
+        h->stage_calls[k] += 1;
     }
-    h->stage_calls += 1;
     h->ring_pending[slot] = 0;
     return hipSuccess;
 }
 
-// Event set for the next profiled call (created on first use).
-hipEvent_t *ring_slot(tr_handle *h)
+int profile_mode(uint32_t flags)
+{
+    return (flags & TR_FLAG_PROFILE) ? 1 : ((flags & TR_FLAG_PROFILE_SC2) ? 2 : 0);
+}
+
+// Event set for the next profiled call (created on first use); mode 1: every
+// stage, 2: the SC2 stage only.
+hipEvent_t *ring_slot(tr_handle *h, int mode)
 {
     if (h->ring.empty()) {
         h->ring.assign((size_t)tr_handle::kRing * (TR_NUM_STAGES + 1), nullptr);
@@ -260,7 +268,7 @@ hipEvent_t *ring_slot(tr_handle *h)
     }
     const int slot = (int)(h->ring_next % tr_handle::kRing);
     if (h->ring_pending[slot] && ring_collect(h, slot) != hipSuccess) return nullptr;
-    h->ring_pending[slot] = 1;
+    h->ring_pending[slot] = (char)mode;
     h->ring_next += 1;
     return &h->ring[(size_t)slot * (TR_NUM_STAGES + 1)];
 }
@@ -374,12 +382,12 @@ tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t 
     if (st != TR_OK) return st;
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
-    const bool profile = (p->flags & TR_FLAG_PROFILE) != 0;
+    const int pmode = profile_mode(p->flags);
     Work w = make_work(h, src, dst, *p, out_dev, mask_dev, learned, 1, n);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t *ev = nullptr;
-    if (profile && !(ev = ring_slot(h))) return TR_ERR_HIP;
-    st = enqueue(h, w, nullptr, n, 1, n, ev, false, s);
+    if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
+    st = enqueue(h, w, nullptr, n, 1, n, ev, pmode, false, s);
     if (st == TR_OK) remember(h, w, 1, s);
     return st;
 }
@@ -393,14 +401,14 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     if (st != TR_OK) return st;
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
-    const bool profile = (p->flags & TR_FLAG_PROFILE) != 0;
+    const int pmode = profile_mode(p->flags);
     Work w = make_work(h, src, dst, *p, out_dev, masks_dev, learned, B, max_n);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (profile || s == nullptr) {
+    if (pmode || s == nullptr) {
         // events (and the legacy default stream) stay out of captured graphs: run eagerly
         hipEvent_t *ev = nullptr;
-        if (profile && !(ev = ring_slot(h))) return TR_ERR_HIP;
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, false, s);
+        if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, pmode, false, s);
         if (st == TR_OK) remember(h, w, B, s);
         return st;
     }
@@ -420,7 +428,7 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_ERR_HIP;
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, false, s);
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, false, s);
         hipError_t ec = hipStreamEndCapture(s, &g);
         if (st != TR_OK || ec != hipSuccess) {
             if (g) hipGraphDestroy(g);
@@ -450,7 +458,7 @@ tr_status tr_features_batch(tr_handle *h, const float *src, const float *dst, co
     q.pool_factor = 1;
     Work w = make_work(h, src, dst, q, h->scratch_out, nullptr, true, B, max_n);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, true, s);
+    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, true, s);
     if (st != TR_OK) return st;
     if (launch_features(w, feat_dev, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s) !=
         hipSuccess)
@@ -525,10 +533,15 @@ tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count)
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     for (int slot = 0; slot < (int)h->ring_pending.size(); ++slot)
         if (h->ring_pending[slot] && ring_collect(h, slot) != hipSuccess) return TR_ERR_HIP;
-    if (h->stage_calls == 0) return TR_ERR_INVALID_ARG;
-    for (int k = 0; k < count; ++k) ms[k] = (float)(h->stage_sum[k] / (double)h->stage_calls);
-    for (double &x : h->stage_sum) x = 0;
-    h->stage_calls = 0;
+    int64_t calls = 0;
+    for (int k = 0; k < TR_NUM_STAGES; ++k) calls += h->stage_calls[k];
+    if (calls == 0) return TR_ERR_INVALID_ARG;
+    for (int k = 0; k < count; ++k)
+        ms[k] = h->stage_calls[k] ? (float)(h->stage_sum[k] / (double)h->stage_calls[k]) : 0.0f;
+    for (int k = 0; k < TR_NUM_STAGES; ++k) {
+        h->stage_sum[k] = 0;
+        h->stage_calls[k] = 0;
+    }
     return TR_OK;
 }
 

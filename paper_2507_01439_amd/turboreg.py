@@ -19,7 +19,7 @@ TR_OK, TR_ERR_INVALID_ARG, TR_ERR_NONFINITE, TR_ERR_NO_HYPOTHESIS = 0, 1, 2, 3
 TR_ERR_WORKSPACE, TR_ERR_HIP, TR_WARN_SCORER_FALLBACK, TR_ERR_NO_SCORER, TR_ERR_BAD_BLOB = 4, 5, 6, 7, 8
 TR_GRAPH_O2, TR_GRAPH_SC2 = 0, 1
 TR_PIVOTS_PLAIN, TR_PIVOTS_LEARNED = 0, 1
-TR_FLAG_PROFILE = 1
+TR_FLAG_PROFILE, TR_FLAG_PROFILE_SC2 = 1, 2
 TR_MAX_K2 = 8
 TR_MLP_NPARAM = 5505
 (TR_TAP_C, TR_TAP_G, TR_TAP_PIVOTS, TR_TAP_CLIQUES, TR_TAP_POSES, TR_TAP_IN, TR_TAP_FEATURES,
