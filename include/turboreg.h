@@ -148,7 +148,7 @@ tr_status tr_train_step(tr_handle *h, const uint16_t *feat_dev, const uint8_t *l
 
 enum {
     TR_TAP_C = 0,         /* N x N uint8 compatibility matrix                          */
-    TR_TAP_G = 1,         /* N x N uint16 O2Graph weights; only i < j is defined        */
+    TR_TAP_G = 1,         /* N x N uint16 O2Graph weights (i < j; the tap zeroes j <= i) */
     TR_TAP_PIVOTS = 2,    /* K x 3 int32 (i, j, w), K = k1 (or the plain pool in learned mode) */
     TR_TAP_CLIQUES = 3,   /* H x 3 int32 (i, j, z), H = k1*k2, slot-major, z = -1 empty  */
     TR_TAP_POSES = 4,     /* H x 12 float32 (R row-major, t)                           */

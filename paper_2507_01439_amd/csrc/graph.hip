@@ -387,6 +387,29 @@ constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then
 // after it; unlike __syncthreads it does not drain the later stages in flight.
 #define SC2_WAIT_BARRIER(N) asm volatile("s_waitcnt vmcnt(" #N ")\n\ts_barrier" ::: "memory")
 
+// Maximum / sum over each half of the wave (lanes 0-31, 32-63), left in lanes 31 and 63: prefix
+// steps inside each 16-lane DPP row, then the last lane of rows 0 and 2 joins rows 1 and 3.
+// Inputs are >= 0, so lanes that receive no value (they read 0) do not change a maximum.
+__device__ __forceinline__ int half_max(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));   // row_bcast:15 into rows 1, 3
+    return v;
+}
+
+__device__ __forceinline__ int half_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+    return v;
+}
+
 // G[i][j] = C_ij * sum_k C_ik C_jk for i < j < n over 256 x 256 output tiles
 // with bi <= bj. C is symmetric, so the product is C C^T and both MFMA
 // operands are rows of C read along k.
@@ -406,10 +429,11 @@ constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then
 //
 // Epilogue: the tile is restaged in LDS as uint16 (weights are below 2^16),
 // then read row-major: masked by C_ij and i < j < n, stored with 16-byte
-// writes, counted into a weight histogram (LDS, added into one of
+// writes (whole chunks: outside i < j < n they hold zeros, which nothing reads), counted into a weight histogram (LDS, added into one of
 // kHistGroups copies per pair) and reduced into the per-row maximum of the
 // upper triangle. In learned mode it also adds row and column sums / maxima
 // of the symmetric SC2 matrix for the per-match features.
+template <bool LEARNED>
 __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -513,7 +537,8 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         // every pair of the tile is in the strict upper triangle and below n: no per-entry test
         const bool interior = bi < bj && (bj + 1) * kSc2Tile <= d.n;
         // thread t: column chunk cc = t % 32 (8 columns) of rows lr = 8k + t / 32, k = 0..31, in four
-        // batches of eight rows; the packed C_ij of the next batch are in flight while one is processed
+        // batches of eight rows; the packed C_ij of the next batch are in flight while one is processed.
+        // Lanes 0-31 of a wave hold one row, lanes 32-63 the next.
         const int cc = tid & 31;
         const int j0 = bj * kSc2Tile + cc * 8;
         const uint8_t *crow = Cb + ((int64_t)bi * kSc2Tile + (tid >> 5)) * rs + j0 / 2;
@@ -527,68 +552,71 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 for (int q = 0; q < 8; ++q)
                     nxt[q] = *reinterpret_cast<const uint32_t *>(crow + (int64_t)(((kb + 1) * 8 + q) * 8) * rs);
             }
+            uint4 tv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                tv[q] = *reinterpret_cast<const uint4 *>(&T[((kb * 8 + q) * 8 + (tid >> 5)) * kSc2Tile + cc * 8]);
+            int rmax[8], rsum[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int lr = (kb * 8 + q) * 8 + (tid >> 5);
                 const int i = bi * kSc2Tile + lr;
-                uint4 *tp = reinterpret_cast<uint4 *>(&T[lr * kSc2Tile + cc * 8]);
-                const uint4 tv = *tp;
-                const uint32_t tw[4] = {tv.x, tv.y, tv.z, tv.w};
+                const uint32_t tw[4] = {tv[q].x, tv[q].y, tv[q].z, tv[q].w};
+                // entries e of the chunk with i < j0 + e < n (all eight except at the diagonal and the edge)
+                const int e_lo = min(8, max(0, i + 1 - j0)), e_hi = min(8, max(0, d.n - j0));
+                const uint32_t vm = interior ? 0xFFu : (((1u << e_hi) - 1u) & ~((1u << e_lo) - 1u));
                 const uint32_t cb = cur[q] >> 1;   // C of column e at bit 4e
                 uint32_t ow[4];
-                if (interior) {
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint32_t lo = (cb >> (8 * k)) & 1u, hi = (cb >> (8 * k + 4)) & 1u;
-                        ow[k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int ja = j0 + 2 * k, jb = ja + 1;
-                        const uint32_t lo = ((cb >> (8 * k)) & 1u) & (uint32_t)(i < ja && ja < d.n);
-                        const uint32_t hi = ((cb >> (8 * k + 4)) & 1u) & (uint32_t)(i < jb && jb < d.n);
-                        ow[k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
-                    }
-                }
-                int rsum = 0;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int v = (int)((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                    if (v > 0) {
-                        if (v < kHistLdsBins) atomicAdd(&hist[v], 1);
-                        else atomicAdd(&gh[v], 1);
-                    }
-                    rsum += v;
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t lo = ((cb >> (8 * k)) & 1u) & (vm >> (2 * k));
+                    const uint32_t hi = ((cb >> (8 * k + 4)) & 1u) & (vm >> (2 * k + 1));
+                    ow[k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
                 }
                 const u16x2 m2 = __builtin_elementwise_max(
                     __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[0]), __builtin_bit_cast(u16x2, ow[1])),
                     __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[2]), __builtin_bit_cast(u16x2, ow[3])));
-                int rmax = max((int)m2.x, (int)m2.y);
-                *tp = make_uint4(ow[0], ow[1], ow[2], ow[3]);   // the masked tile, for the learned column pass
-                if (interior) {
-                    *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-                } else if (i < d.n && j0 + 7 > i && j0 < d.n) {
-                    if (j0 > i && j0 + 8 <= d.n) {
-                        *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-                    } else {
+                rmax[q] = max((int)m2.x, (int)m2.y);
+                rsum[q] = 0;
+                if (LEARNED) {
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int j = j0 + e;
-                            if (i < j && j < d.n) Gb[(int64_t)i * d.npad + j] = (uint16_t)(ow[e >> 1] >> (16 * (e & 1)));
-                        }
+                    for (int e = 0; e < 8; ++e) rsum[q] += (int)((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                    // the masked tile, for the column pass
+                    *reinterpret_cast<uint4 *>(&T[lr * kSc2Tile + cc * 8]) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                }
+                // every chunk is stored whole: entries with j <= i or j >= n are zero and no reader looks at them
+                *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                // weight histogram: only as many LDS atomics as the lane with the most nonzero weights needs
+                uint32_t nz = 0;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) nz |= (uint32_t)(((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) != 0) << e;
+                while (__any(nz)) {
+                    if (nz) {
+                        const int e = __builtin_ctz(nz);
+                        nz &= nz - 1;
+                        const uint32_t word = (e >> 1) == 0 ? ow[0] : (e >> 1) == 1 ? ow[1] : (e >> 1) == 2 ? ow[2] : ow[3];
+                        const int v = (int)((word >> (16 * (e & 1))) & 0xFFFFu);
+                        if (v < kHistLdsBins) atomicAdd(&hist[v], 1);
+                        else atomicAdd(&gh[v], 1);
                     }
                 }
+            }
+            // row maxima (and sums) over the 32 lanes of each row, eight rows interleaved (DPP, no LDS)
 #pragma unroll
-                for (int o = 16; o > 0; o >>= 1) {
-                    rmax = max(rmax, __shfl_xor(rmax, o, 64));
-                    rsum += __shfl_xor(rsum, o, 64);
-                }
-                if ((tid & 31) == 0 && rmax > 0) {
-                    atomicMax(&rowmax[i], rmax);
-                    if (w.learned) {
-                        atomicAdd(&rstat[i * 20 + 1], rsum);
-                        atomicMax(&rstat[i * 20 + 2], rmax);
+            for (int q = 0; q < 8; ++q) {
+                rmax[q] = half_max(rmax[q]);
+                if (LEARNED) rsum[q] = half_sum(rsum[q]);
+            }
+            if ((lane & 31) == 31) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int i = bi * kSc2Tile + (kb * 8 + q) * 8 + (tid >> 5);
+                    if (rmax[q] > 0) {
+                        atomicMax(&rowmax[i], rmax[q]);
+                        if (LEARNED) {
+                            atomicAdd(&rstat[i * 20 + 1], rsum[q]);
+                            atomicMax(&rstat[i * 20 + 2], rmax[q]);
+                        }
                     }
                 }
             }
@@ -597,7 +625,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
             }
         }
-        if (w.learned) {   // column j of the upper tile is row j of the lower one (Ghat is symmetric)
+        if (LEARNED) {   // column j of the upper tile is row j of the lower one (Ghat is symmetric)
             __syncthreads();
             const int j = bj * kSc2Tile + tid;
             int csum = 0, cmax = 0;
@@ -649,14 +677,19 @@ hipError_t launch_compat(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sc2, dim3(grid), dim3(256), kSc2Lds, s, w);
+    if (w.learned) hipLaunchKernelGGL(k_sc2<true>, dim3(grid), dim3(256), kSc2Lds, s, w);
+    else hipLaunchKernelGGL(k_sc2<false>, dim3(grid), dim3(256), kSc2Lds, s, w);
     return hipGetLastError();
 }
 
 hipError_t setup_graph_kernels()
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kSc2Lds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kSc2Lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                kSc2Lds);
+    return e;
 }
 
 }  // namespace tr

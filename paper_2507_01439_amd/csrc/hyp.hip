@@ -252,7 +252,8 @@ __global__ void __launch_bounds__(256) k_cliques(Work w, int total)
         const int b = item / w.k1, p = item - b * w.k1;
         const PairDesc d = w.pairs[b];
         const int32_t *pv = w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
-        const int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
+        int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
+        if (i < 0 || j < 0 || i >= d.n || j >= d.n || i == j) i = j = -1;   // an empty slot (or a bad index) finds no clique
         int32_t *cl = w.cliques + (int64_t)b * w.h_cap * 3;
         uint64_t top[KMAX];
 #pragma unroll

@@ -524,7 +524,13 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
     hipError_t e;
     if (rows) e = hipMemcpy2D(host_dst, width, srcp, pitch, width, rows, hipMemcpyDeviceToHost);
     else e = hipMemcpy(host_dst, srcp, need, hipMemcpyDeviceToHost);
-    return e == hipSuccess ? TR_OK : TR_ERR_HIP;
+    if (e != hipSuccess) return TR_ERR_HIP;
+    if (tap == TR_TAP_G) {   // the device holds only i < j; the tap is the O2Graph, zero elsewhere
+        uint16_t *g = static_cast<uint16_t *>(host_dst);
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j <= i; ++j) g[i * n + j] = 0;
+    }
+    return TR_OK;
 }
 
 tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count)
