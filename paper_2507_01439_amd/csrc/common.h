@@ -32,7 +32,7 @@ struct PairDesc {
 // Per-pair scalars written by the kernels.
 struct PairState {
     int32_t status;     // tr_status
-    int32_t nonfinite;  // 1 if any coordinate is NaN/Inf
+    int32_t nonfinite;  // 1 if any coordinate is NaN/Inf (summed from the compatibility tiles)
     int32_t n_boundary;
     int32_t n_edges;
     int32_t alpha;      // weight of the last pivot (the K-th largest, Eq. 4)
@@ -43,6 +43,8 @@ struct PairState {
     int32_t ncand;      // keys the sort ranks (fast: c_gt + all ties; else K)
     int32_t cand_cnt;   // keys collected so far (fast path)
     int32_t done;       // workgroups of a fused stage that have finished this pair
+    int32_t n_valid;    // hypotheses with a clique
+    uint64_t best;      // max over hypotheses of (IN + 1) << 32 | (2^32 - 1 - h); 0: none
 };
 
 struct Plan {
@@ -58,6 +60,7 @@ struct Work {
     const Plan *plan;
     const int32_t *pre;       // kNumPrefix x (max_batch + 1)
     int32_t pre_stride;       // max_batch + 1
+    int32_t n1;               // N of a single-pair call (its plan is computed in registers), 0 for a batch
     int32_t max_n;            // per-pair row stride of the per-row arenas
     int32_t k1, k2, pool;     // pool = plain pivots selected (k1, or pool_factor*k1 in learned mode)
     int32_t H;                // k1 * k2 hypotheses per pair
@@ -67,7 +70,7 @@ struct Work {
     uint16_t *G;              // G arena
     int32_t *ghist;           // max_batch x kHistGroups x max_n weight histograms (filled by the SC2 epilogue)
     int32_t *rowmax;          // max_batch x max_n: max_{j>i} G_ij (filled by the SC2 epilogue)
-    int32_t *cnt_part;        // per compatibility work item: (boundary pairs, edges)
+    int32_t *cnt_part;        // per compatibility work item: (boundary pairs, edges, non-finite input)
     int32_t *rowcnt;          // max_batch x max_n x 2 (count > alpha, count == alpha)
     uint64_t *rowseg;         // max_batch x max_n: bit s set if the row's s-th 512-column segment (counted
                               // from its first column j > i) holds a pair of weight >= alpha
@@ -90,6 +93,7 @@ struct Work {
     int32_t learned;          // learned pivot mode / feature accumulation on
 };
 
+
 // Largest b in [0, B) with pre[b] <= item (pre is non-decreasing, pre[0] = 0).
 __device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)
 {
@@ -99,6 +103,72 @@ __device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)
         if (pre[mid] <= item) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Per-pair sizes of a valid pair (3 <= n <= max_n): the descriptor and the
+// work items of every stage. The device planner and single-pair calls (which
+// compute their plan in registers) use the same formulas.
+__host__ __device__ inline PairDesc pair_desc_of(int32_t n, int32_t pt_off, int64_t arena_off, int32_t pool)
+{
+    PairDesc d;
+    d.n = n;
+    d.npad = (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
+    d.pt_off = pt_off;
+    const int64_t pairs_all = (int64_t)n * (n - 1) / 2;
+    d.kpiv = (int32_t)(pairs_all < pool ? pairs_all : pool);
+    d.c_off = arena_off;
+    d.g_off = arena_off;
+    return d;
+}
+
+__host__ __device__ inline int64_t stage_items(int stage, int32_t n, int32_t H)
+{
+    const int64_t npad = (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
+    const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
+    switch (stage) {
+    case kPrep: return (n + kPrepRows - 1) / kPrepRows;
+    case kCompat: return nb64 * (nb64 + 1) / 2;
+    case kSc2: return nbs * (nbs + 1) / 2;
+    case kRowBlk: return (n + kRowsPerItem - 1) / kRowsPerItem;
+    default: return (int64_t)((H + kScoreHyp - 1) / kScoreHyp) * ((n + kScorePts - 1) / kScorePts);
+    }
+}
+
+// Work lists: all items of a stage, pair after pair. A single-pair call (n1 > 0)
+// derives everything from n1; a batch reads the device plan.
+__device__ __forceinline__ int stage_total(const Work &w, int stage)
+{
+    return w.n1 ? (int)stage_items(stage, w.n1, w.H) : w.plan->total[stage];
+}
+
+// The pair an item belongs to, and the item's index inside that pair.
+__device__ __forceinline__ int stage_pair(const Work &w, int stage, int item, int &local)
+{
+    if (w.n1) {
+        local = item;
+        return 0;
+    }
+    const int32_t *pre = w.pre + stage * w.pre_stride;
+    const int b = find_pair(pre, w.plan->B, item);
+    local = item - pre[b];
+    return b;
+}
+
+// First item of pair b in a stage's list, and its item count.
+__device__ __forceinline__ int stage_first(const Work &w, int stage, int b)
+{
+    return w.n1 ? 0 : w.pre[stage * w.pre_stride + b];
+}
+
+__device__ __forceinline__ int stage_count(const Work &w, int stage, int b)
+{
+    return w.n1 ? (int)stage_items(stage, w.n1, w.H)
+                : w.pre[stage * w.pre_stride + b + 1] - w.pre[stage * w.pre_stride + b];
+}
+
+__device__ __forceinline__ PairDesc pair_desc(const Work &w, int b)
+{
+    return w.n1 ? pair_desc_of(w.n1, 0, 0, w.pool) : w.pairs[b];
 }
 
 // Ascending bitonic sort of P keys in LDS by one workgroup (P a power of two,
@@ -142,8 +212,8 @@ hipError_t launch_compat(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
 hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
-hipError_t launch_cliques(const Work &w, int B, hipStream_t s);
-hipError_t launch_score(const Work &w, int grid, hipStream_t s);
+hipError_t launch_hyp(const Work &w, int B, int num_cus, hipStream_t s);
+hipError_t setup_hyp_kernels();
 
 // Once per process and device, before any launch (and so outside stream capture):
 // raise the dynamic-LDS limits of the kernels that need more than 64 KiB.

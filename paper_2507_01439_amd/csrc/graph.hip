@@ -114,28 +114,16 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
             else n = n_single;
             ok = n >= 3 && n <= max_n;
         }
-        const int32_t nn = ok ? n : 0;
         const int32_t npad = ok ? (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile : 0;
-        const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
         int64_t cnt[NV], excl[NV], tot[NV];
-        cnt[kPrep] = (nn + kPrepRows - 1) / kPrepRows;
-        cnt[kCompat] = nb64 * (nb64 + 1) / 2;
-        cnt[kSc2] = nbs * (nbs + 1) / 2;
-        cnt[kRowBlk] = (nn + kRowsPerItem - 1) / kRowsPerItem;
-        // an invalid pair still gets one (empty) scoring item: its last workgroup writes the result record
-        cnt[kScore] = ok ? (int64_t)((H + kScoreHyp - 1) / kScoreHyp) * ((nn + kScorePts - 1) / kScorePts) : (b < B);
-        cnt[kNumPrefix] = (int64_t)npad * npad;   // arena bytes
+        for (int s = 0; s < kNumPrefix; ++s) cnt[s] = ok ? stage_items(s, n, H) : 0;
+        cnt[kScore] = ok ? cnt[kScore] : (b < B);   // an invalid pair's one (empty) scoring item writes its record
+        cnt[kNumPrefix] = (int64_t)npad * npad;   // arena entries
         block_scan_multi<NV>(cnt, excl, tot, lds);
         if (b < B) {
             for (int s = 0; s < kNumPrefix; ++s) pre[s * pre_stride + b] = (int32_t)(excl[s] + carry[s]);
-            PairDesc d;
-            d.n = nn;
-            d.npad = npad;
-            d.pt_off = pt;
-            const int64_t pairs_all = (int64_t)nn * (nn - 1) / 2;
-            d.kpiv = (int32_t)(pairs_all < pool ? pairs_all : pool);
-            d.c_off = excl[kNumPrefix] + carry[kNumPrefix];
-            d.g_off = d.c_off;
+            PairDesc d = pair_desc_of(n, pt, excl[kNumPrefix] + carry[kNumPrefix], pool);
+            if (!ok) d.n = d.npad = d.kpiv = 0;
             pairs[b] = d;
             PairState st = {};
             st.status = ok ? TR_OK : TR_ERR_INVALID_ARG;
@@ -156,12 +144,12 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
 // Learned mode: zero the per-row feature accumulators.
 __global__ void __launch_bounds__(256) k_prep_learned(Work w)
 {
-    const int total = w.plan->total[kPrep], B = w.plan->B;
-    const int32_t *pre = w.pre + kPrep * w.pre_stride;
+    const int total = stage_total(w, kPrep);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
-        const int i = (item - pre[b]) * kPrepRows + threadIdx.x;
-        if (i < w.pairs[b].n) {
+        int local;
+        const int b = stage_pair(w, kPrep, item, local);
+        const int i = local * kPrepRows + threadIdx.x;
+        if (i < pair_desc(w, b).n) {
             int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
             for (int f = 0; f < 20; ++f) rs[f] = 0;
         }
@@ -207,7 +195,7 @@ __device__ __forceinline__ bool near_tau(float la, float lb, float dl, float tau
 // LDS and written to both triangles with 16-byte stores. The next item's
 // points are loaded while the current one is computed. Per-tile counts
 // (boundary pairs, edges) go to a per-item slot, so no atomics are needed;
-// non-finite inputs are flagged by the diagonal tiles, which also clear the
+// non-finite inputs are counted by the diagonal tiles (third slot), which also clear the
 // pair's weight histograms and row maxima for their rows.
 template <bool LEARNED>
 __global__ void __launch_bounds__(256, 2) k_compat(Work w)
@@ -215,19 +203,19 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
     __shared__ float px[2][64][3], py[2][64][3];
     __shared__ __attribute__((aligned(16))) uint8_t tile[2][64 * kNibStride];
     __shared__ int32_t hrow[LEARNED ? 64 : 1][17], hcol[LEARNED ? 64 : 1][17];
-    __shared__ int32_t red[4][2];
-    const int total = w.plan->total[kCompat], B = w.plan->B;
-    const int32_t *pre = w.pre + kCompat * w.pre_stride;
+    __shared__ int32_t red[4][3];
+    const int total = stage_total(w, kCompat);
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63, wv = tid >> 6;
     const float tau = w.tau, q = tau * 0.25f;
     // prefetch registers: thread t < 128 holds point (t & 63) of side t >> 6
     float nx[3] = {0, 0, 0}, ny[3] = {0, 0, 0};
     auto fetch = [&](int item) {
         if (tid < 128 && item < total) {
-            const int b = find_pair(pre, B, item);
-            const PairDesc d = w.pairs[b];
+            int local;
+            const int b = stage_pair(w, kCompat, item, local);
+            const PairDesc d = pair_desc(w, b);
             int bi, bj;
-            tri_decode(item - pre[b], d.npad / kCompatTile, bi, bj);
+            tri_decode(local, d.npad / kCompatTile, bi, bj);
             const int i = ((tid >> 6) ? bj : bi) * kCompatTile + (tid & 63);
             for (int k = 0; k < 3; ++k) {
                 nx[k] = i < d.n ? w.src[3 * (int64_t)(d.pt_off + i) + k] : 0.0f;
@@ -235,12 +223,18 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
             }
         }
     };
+    if (w.n1 && blockIdx.x == 0 && tid == 0) {   // a single-pair call has no planner: reset its state here
+        PairState st = {};
+        st.status = TR_OK;
+        w.state[0] = st;
+    }
     fetch(blockIdx.x);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
+        int local;
+        const int b = stage_pair(w, kCompat, item, local);
+        const PairDesc d = pair_desc(w, b);
         int bi, bj;
-        tri_decode(item - pre[b], d.npad / kCompatTile, bi, bj);
+        tri_decode(local, d.npad / kCompatTile, bi, bj);
         const bool diag = bi == bj;
         bool bad = false;
         if (tid < 128) {
@@ -261,7 +255,7 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) { hrow[k / 17][k % 17] = 0; hcol[k / 17][k % 17] = 0; }
         }
-        if (__any(bad) && lane == 0) atomicOr(&w.state[b].nonfinite, 1);
+        const bool any_bad = __any(bad);
         __syncthreads();
         fetch(item + gridDim.x);
         float dl[4][4];
@@ -339,7 +333,7 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
             *reinterpret_cast<uint16_t *>(&tile[1][(tx * 4 + e) * kNibStride + ty * 2]) = (uint16_t)pack_e2m1(colbits[e]);
         nbnd = wave_sum(nbnd);
         nedge = wave_sum(nedge);
-        if (lane == 0) { red[wv][0] = nbnd; red[wv][1] = nedge; }
+        if (lane == 0) { red[wv][0] = nbnd; red[wv][1] = nedge; red[wv][2] = any_bad; }
         __syncthreads();
         uint8_t *Cb = w.C + d.c_off / 2;   // packed rows of npad / 2 bytes
         const int64_t rs = d.npad / 2;
@@ -349,7 +343,7 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         if (!diag)
             *reinterpret_cast<uint2 *>(Cb + ((int64_t)bj * kCompatTile + r) * rs + bi * (kCompatTile / 2) + c8) =
                 *reinterpret_cast<const uint2 *>(&tile[1][r * kNibStride + c8]);
-        if (tid < 2) w.cnt_part[2 * (int64_t)item + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+        if (tid < 3) w.cnt_part[3 * (int64_t)item + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
         if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) {
                 const int rr = k / 17, f = k % 17;
@@ -439,8 +433,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     int32_t *hist = reinterpret_cast<int32_t *>(smem + kRingBytes);
     uint16_t *T = reinterpret_cast<uint16_t *>(smem);
-    const int total = w.plan->total[kSc2], B = w.plan->B;
-    const int32_t *pre = w.pre + kSc2 * w.pre_stride;
+    const int total = stage_total(w, kSc2);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
     const int xcd = blockIdx.x & 7, nx = (gridDim.x - xcd + 7) >> 3, lb = blockIdx.x >> 3;
     const int chunk = (total + 7) >> 3;
@@ -451,10 +444,11 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
     for (int k = tid; k < kHistLdsBins; k += 256) hist[k] = 0;
     __syncthreads();
     for (int item = xcd * chunk + lb; item < end; item += nx) {
-        const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
+        int local;
+        const int b = stage_pair(w, kSc2, item, local);
+        const PairDesc d = pair_desc(w, b);
         int bi, bj;
-        super_decode(item - pre[b], d.npad / kSc2Tile, bi, bj);
+        super_decode(local, d.npad / kSc2Tile, bi, bj);
         const uint8_t *Cb = w.C + d.c_off / 2;
         const int64_t rs = d.npad / 2;       // packed row bytes
         const int nk = (int)(rs / kBK);
@@ -530,12 +524,13 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 }
             }
         __syncthreads();
-        int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + (item - pre[b]) % kHistGroups) * w.max_n;
+        int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + local % kHistGroups) * w.max_n;
         int32_t *rowmax = w.rowmax + (int64_t)b * w.max_n;
         int32_t *rstat = w.rowstat + (int64_t)b * w.max_n * 20;
         uint16_t *Gb = w.G + d.g_off;
         // every pair of the tile is in the strict upper triangle and below n: no per-entry test
         const bool interior = bi < bj && (bj + 1) * kSc2Tile <= d.n;
+        const bool small_n = d.n <= kHistLdsBins;
         // thread t: column chunk cc = t % 32 (8 columns) of rows lr = 8k + t / 32, k = 0..31, in four
         // batches of eight rows; the packed C_ij of the next batch are in flight while one is processed.
         // Lanes 0-31 of a wave hold one row, lanes 32-63 the next.
@@ -586,18 +581,27 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 }
                 // every chunk is stored whole: entries with j <= i or j >= n are zero and no reader looks at them
                 *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-                // weight histogram: only as many LDS atomics as the lane with the most nonzero weights needs
+                // weight histogram: one LDS atomic per nonzero weight, round by round (a lane's next
+                // nonzero each round), as many rounds as the lane with the most nonzero weights needs
                 uint32_t nz = 0;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) nz |= (uint32_t)(((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) != 0) << e;
-                while (__any(nz)) {
-                    if (nz) {
-                        const int e = __builtin_ctz(nz);
-                        nz &= nz - 1;
-                        const uint32_t word = (e >> 1) == 0 ? ow[0] : (e >> 1) == 1 ? ow[1] : (e >> 1) == 2 ? ow[2] : ow[3];
-                        const int v = (int)((word >> (16 * (e & 1))) & 0xFFFFu);
-                        if (v < kHistLdsBins) atomicAdd(&hist[v], 1);
-                        else atomicAdd(&gh[v], 1);
+                auto next_weight = [&]() -> int {
+                    const int e = __builtin_ctz(nz);
+                    nz &= nz - 1;
+                    const uint32_t word = (e >> 1) == 0 ? ow[0] : (e >> 1) == 1 ? ow[1] : (e >> 1) == 2 ? ow[2] : ow[3];
+                    return (int)((word >> (16 * (e & 1))) & 0xFFFFu);
+                };
+                if (small_n) {   // every weight is below n <= kHistLdsBins
+                    while (__any(nz))
+                        if (nz) atomicAdd(&hist[next_weight()], 1);
+                } else {
+                    while (__any(nz)) {
+                        if (nz) {
+                            const int v = next_weight();
+                            if (v < kHistLdsBins) atomicAdd(&hist[v], 1);
+                            else atomicAdd(&gh[v], 1);
+                        }
                     }
                 }
             }

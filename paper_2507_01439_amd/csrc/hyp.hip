@@ -72,17 +72,14 @@ __device__ __forceinline__ void adj_col(const double (&A)[4][4], double (&v)[4])
 // eigenvector is the largest column of adj(K - lambda I). When that column
 // vanishes (a repeated top eigenvalue: collinear or coincident points) the
 // cyclic Jacobi method on K decides instead. float64 throughout, then R and t
-// are rounded to float32. IN is initialised here (0, or -1 for an empty clique).
-__device__ void fit_pose(const Work &w, const PairDesc &d, int64_t slot, int ia, int ib, int ic)
+// are rounded to float32. An empty clique (z < 0) gives the identity and false.
+__device__ bool fit_pose(const Work &w, const PairDesc &d, int ia, int ib, int ic, float (&pose)[12])
 {
     {
-        float *pose = w.poses + slot * 12;
-        int32_t *inl = w.inl + slot;
         if (d.n == 0 || ic < 0) {
 #pragma unroll
             for (int k = 0; k < 12; ++k) pose[k] = (k < 9 && k % 4 == 0) ? 1.0f : 0.0f;
-            *inl = -1;
-            return;
+            return false;
         }
         const int idx[3] = {ia, ib, ic};
         double P[3][3], Q[3][3], pb[3] = {0, 0, 0}, qb[3] = {0, 0, 0};
@@ -202,7 +199,7 @@ __device__ void fit_pose(const Work &w, const PairDesc &d, int64_t slot, int ia,
 #pragma unroll
         for (int r = 0; r < 3; ++r)
             pose[9 + r] = (float)(qb[r] - (R[3 * r] * pb[0] + R[3 * r + 1] * pb[1] + R[3 * r + 2] * pb[2]));
-        *inl = 0;
+        return true;
     }
 }
 
@@ -236,21 +233,19 @@ __device__ __forceinline__ void top_insert(uint64_t (&top)[KMAX], uint64_t k)
     }
 }
 
-// One wavefront per pivot. On the O2Graph each lane reads eight consecutive
+// One wavefront per pivot (p of pair b). On the O2Graph each lane reads eight consecutive
 // weights of rows i and j with one 16-byte load each (the wave covers 512
 // third vertices per step, z > j only); on the undirected graph lanes stride
 // over z and read the lower triangle through the transpose. Each lane keeps
 // its KMAX best keys sorted in registers (compare-and-swap insertion, no
 // dynamic register indexing); K2 rounds of a wave-wide max then pick the
-// pivot's cliques in (S desc, z asc) order.
+// pivot's cliques in (S desc, z asc) order and writes them (slot-major);
+// lane s < K2 returns the third vertex of clique s (-1: none), pi / pj the
+// pivot (-1 for an empty slot).
 template <int KMAX>
-__global__ void __launch_bounds__(256) k_cliques(Work w, int total)
+__device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, int lane, int &pi, int &pj)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave0 = blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = gridDim.x * 4;
-    for (int item = wave0; item < total; item += nwaves) {
-        const int b = item / w.k1, p = item - b * w.k1;
-        const PairDesc d = w.pairs[b];
+    {
         const int32_t *pv = w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
         int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
         if (i < 0 || j < 0 || i >= d.n || j >= d.n || i == j) i = j = -1;   // an empty slot (or a bad index) finds no clique
@@ -262,28 +257,33 @@ __global__ void __launch_bounds__(256) k_cliques(Work w, int total)
             const uint16_t *G = w.G + d.g_off;
             const int64_t npad = d.npad;
             const int wij = i < j ? G[i * npad + j] : G[(int64_t)j * npad + i];
-            if (wij > 0 && w.graph == TR_GRAPH_O2) {
+            if (w.graph == TR_GRAPH_O2) {
                 const uint16_t *ri = G + i * npad, *rj = G + (int64_t)j * npad;
                 const int c1 = (d.n + 7) >> 3;
-                // two chunks per lane in flight: 1024 third vertices per wave step
-                for (int c = ((j + 1) >> 3) + lane; c < c1; c += 128) {
-                    const bool two = c + 64 < c1;
-                    const uint4 qi = *reinterpret_cast<const uint4 *>(ri + 8 * c);
-                    const uint4 qj = *reinterpret_cast<const uint4 *>(rj + 8 * c);
-                    uint4 pi = make_uint4(0, 0, 0, 0), pj = make_uint4(0, 0, 0, 0);
-                    if (two) {
-                        pi = *reinterpret_cast<const uint4 *>(ri + 8 * (c + 64));
-                        pj = *reinterpret_cast<const uint4 *>(rj + 8 * (c + 64));
-                    }
-                    const uint32_t ui[8] = {qi.x, qi.y, qi.z, qi.w, pi.x, pi.y, pi.z, pi.w};
-                    const uint32_t uj[8] = {qj.x, qj.y, qj.z, qj.w, pj.x, pj.y, pj.z, pj.w};
+                // sixteen chunks of each row per lane in flight (every z of a row up to N = 8192 at
+                // once), issued together with w_ij
+                for (int c0 = ((j + 1) >> 3); c0 < c1; c0 += 1024) {
+                    uint4 qi[16], qj[16];
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int z = 8 * (c + (e >> 3) * 64) + (e & 7);
-                        const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                        const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                        if (z > j && z < d.n && giz > 0 && gjz > 0)
-                            top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
+                    for (int u = 0; u < 16; ++u) {
+                        const int c = c0 + 64 * u + lane;
+                        qi[u] = c < c1 ? *reinterpret_cast<const uint4 *>(ri + 8 * c) : make_uint4(0, 0, 0, 0);
+                        qj[u] = c < c1 ? *reinterpret_cast<const uint4 *>(rj + 8 * c) : make_uint4(0, 0, 0, 0);
+                    }
+                    if (wij == 0) continue;   // not an edge: no clique (Eq. 8)
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int c = c0 + 64 * u + lane;
+                        const uint32_t ui[4] = {qi[u].x, qi[u].y, qi[u].z, qi[u].w};
+                        const uint32_t uj[4] = {qj[u].x, qj[u].y, qj[u].z, qj[u].w};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int z = 8 * c + e;
+                            const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                            const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                            if (z > j && z < d.n && giz > 0 && gjz > 0)
+                                top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
+                        }
                     }
                 }
             } else if (wij > 0) {
@@ -313,8 +313,9 @@ __global__ void __launch_bounds__(256) k_cliques(Work w, int total)
                 cl[3 * h + 2] = z;
             }
         }
-        // one rigid fit per clique (Section 3.5), on lanes 0..K2-1
-        if (lane < w.k2) fit_pose(w, d, (int64_t)b * w.h_cap + (int64_t)lane * w.k1 + p, i, j, zmine);
+        pi = i;
+        pj = j;
+        return zmine;
     }
 }
 
@@ -363,52 +364,20 @@ __device__ __forceinline__ int row16_scan(int v)
 // workgroup.
 __device__ void select_pair(const Work &w, int b)
 {
-    __shared__ uint64_t red[4];
-    __shared__ int32_t cnt[4][3];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const PairDesc d = w.pairs[b];
+    const int tid = threadIdx.x;
+    const PairDesc d = pair_desc(w, b);
+    // the argmax and the counts were folded into the pair's state by atomics of this launch
+    const uint64_t best = __hip_atomic_load(&w.state[b].best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int nvalid = __hip_atomic_load(&w.state[b].n_valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const PairState st = w.state[b];
-    uint64_t best = 0;
-    int nvalid = 0, nbnd = 0, nedge = 0;
-    if (d.n > 0) {
-        const int32_t *inl = w.inl + (int64_t)b * w.h_cap;
-        for (int h = tid; h < w.H; h += 256) {
-            const int v = __atomic_load_n(&inl[h], __ATOMIC_RELAXED);   // written by other workgroups
-            if (v >= 0) {
-                ++nvalid;
-                const uint64_t k = ((uint64_t)(v + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
-                best = k > best ? k : best;
-            }
-        }
-        const int32_t *pre = w.pre + kCompat * w.pre_stride;
-        for (int t = pre[b] + tid; t < pre[b + 1]; t += 256) {
-            nbnd += w.cnt_part[2 * (int64_t)t];
-            nedge += w.cnt_part[2 * (int64_t)t + 1];
-        }
-    }
-    best = wave_max_u64(best);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        nvalid += __shfl_xor(nvalid, o, 64);
-        nbnd += __shfl_xor(nbnd, o, 64);
-        nedge += __shfl_xor(nedge, o, 64);
-    }
-    if (lane == 0) { red[wv] = best; cnt[wv][0] = nvalid; cnt[wv][1] = nbnd; cnt[wv][2] = nedge; }
-    __syncthreads();
-    best = 0;
-    nvalid = nbnd = nedge = 0;
-    for (int k = 0; k < 4; ++k) {
-        best = red[k] > best ? red[k] : best;
-        nvalid += cnt[k][0];
-        nbnd += cnt[k][1];
-        nedge += cnt[k][2];
-    }
+    const int nbnd = st.n_boundary, nedge = st.n_edges, nbad = st.nonfinite;
     const int hbest = best ? (int)(0xFFFFFFFFu - (uint32_t)best) : -1;
     float ps[12];
     if (hbest >= 0) {
-        const float *pose = w.poses + ((int64_t)b * w.h_cap + hbest) * 12;
+        const uint32_t *pose = reinterpret_cast<const uint32_t *>(w.poses + ((int64_t)b * w.h_cap + hbest) * 12);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) ps[k] = pose[k];
+        for (int k = 0; k < 12; ++k)   // written by other workgroups of this launch
+            ps[k] = __uint_as_float(__hip_atomic_load(pose + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     } else {
 #pragma unroll
         for (int k = 0; k < 12; ++k) ps[k] = (k < 9 && k % 4 == 0) ? 1.0f : 0.0f;
@@ -422,7 +391,7 @@ __device__ void select_pair(const Work &w, int b)
         r.n_valid_hyp = nvalid;
         int status = TR_OK;
         if (st.status == TR_ERR_INVALID_ARG) status = TR_ERR_INVALID_ARG;
-        else if (st.nonfinite) status = TR_ERR_NONFINITE;
+        else if (nbad) status = TR_ERR_NONFINITE;
         else if (hbest < 0) status = TR_ERR_NO_HYPOTHESIS;
         else if (st.fallback) status = TR_WARN_SCORER_FALLBACK;
         r.status = status;
@@ -443,87 +412,144 @@ __device__ void select_pair(const Work &w, int b)
     }
 }
 
-// Work item = kScoreHyp (64) hypotheses x kScorePts (256) matches of one
-// pair. The matches are staged in LDS; thread (q, l) holds the four poses
-// 4q .. 4q+3 in registers and scores them on matches l, l+16, ..., so every
-// LDS read serves four residuals. The 16 partial counts of a pose (one DPP
-// row) are summed in registers and added to IN with one integer atomic, so
-// the result does not depend on the order. The workgroup that finishes the
-// last item of a pair (atomic ticket, no waiting) then selects the pair's
-// result.
-__global__ void __launch_bounds__(256) k_score(Work w)
+// Sum over the 64 lanes (DPP), valid in every lane.
+__device__ __forceinline__ int wave_total(int v)
 {
-    __shared__ float4 pts[kScorePts][2];
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ __forceinline__ void store_agent(float *p, float v)
+{
+    __hip_atomic_store(reinterpret_cast<uint32_t *>(p), __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Hypotheses of ppw pivots per work item (item = pair b, pivots g*ppw ..):
+// wave v finds the cliques of pivots v, v+4, ... (Eqs. 5-8) and lanes 0..K2-1
+// fit their poses (Section 3.5) into LDS; then the whole workgroup scores the
+// item's ppw*K2 hypotheses against all N matches of the pair (Eq. 9), each
+// thread reading its matches from L2 (two per step, four steps of loads in
+// flight) and evaluating eight poses held in registers per pass; wave sums
+// (DPP) are added into per-hypothesis LDS totals, so IN needs no global
+// atomics. IN and the poses are stored at device scope and each item folds
+// its best (IN, h) and valid count into the pair's state; the workgroup that
+// finishes a pair's last item (atomic ticket, no waiting) selects the result.
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
+{
+    __shared__ float pose_l[16 * TR_MAX_K2][12];
+    __shared__ int32_t valid_l[16 * TR_MAX_K2], tot_l[16 * TR_MAX_K2];
     __shared__ int32_t last;
-    const int total = w.plan->total[kScore], B = w.plan->B;
-    const int32_t *pre = w.pre + kScore * w.pre_stride;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int ipp = (w.k1 + ppw - 1) / ppw, total = B * ipp;
     const float th2 = w.theta * w.theta;
-    const int tid = threadIdx.x, q = tid >> 4, l = tid & 15;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
-        const int npc = max(1, (d.n + kScorePts - 1) / kScorePts);
-        const int local = item - pre[b], hb = local / npc, pc = local - hb * npc;
-        const int k0 = pc * kScorePts, cnt = max(0, min(kScorePts, d.n - k0));
-        if (tid < cnt) {
-            const int64_t g = d.pt_off + k0 + tid;
-            pts[tid][0] = make_float4(w.src[3 * g], w.src[3 * g + 1], w.src[3 * g + 2], 0.0f);
-            pts[tid][1] = make_float4(w.dst[3 * g], w.dst[3 * g + 1], w.dst[3 * g + 2], 0.0f);
-        }
-        float ps[4][12];
-        bool live[4];
-        int32_t *inl = w.inl + (int64_t)b * w.h_cap;
+        const int b = item / ipp, g = item - b * ipp;
+        const PairDesc d = pair_desc(w, b);
+        const int nloc = ppw * w.k2;   // local hypothesis hl = (pivot lp) * K2 + slot
+        if (tid < 16 * TR_MAX_K2) tot_l[tid] = 0;
+        for (int r = 0; r < ppw / 4; ++r) {
+            const int lp = r * 4 + wv, p = g * ppw + lp;
+            int pi = -1, pj = -1, z = -1;
+            if (p < w.k1) z = clique_search<KMAX>(w, d, b, p, lane, pi, pj);
+            if (lane < w.k2) {
+                float pose[12];
+                const bool ok = p < w.k1 && fit_pose(w, d, pi, pj, z, pose);
+                const int hl = lp * w.k2 + lane;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int h = hb * kScoreHyp + 4 * q + u;
-            live[u] = h < w.H && inl[h] >= 0;
-            const float *pose = w.poses + ((int64_t)b * w.h_cap + min(h, w.H - 1)) * 12;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) ps[u][k] = pose[k];
+                for (int k = 0; k < 12; ++k) pose_l[hl][k] = pose[k];
+                valid_l[hl] = ok;
+            }
         }
         __syncthreads();
-        int c[4] = {0, 0, 0, 0};
-        for (int k = l; k < cnt; k += 16) {
-            const float4 x = pts[k][0], y = pts[k][1];
+        for (int h0 = 0; h0 < nloc; h0 += 8) {
+            float ps[8][12];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) c[u] += residual2(ps[u], x.x, x.y, x.z, y.x, y.y, y.z) <= th2;
-        }
+            for (int u = 0; u < 8; ++u) {
+                const int hl = min(h0 + u, nloc - 1);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            c[u] = row16_scan(c[u]);
-            if (l == 15 && live[u] && c[u]) atomicAdd(&inl[hb * kScoreHyp + 4 * q + u], c[u]);
+                for (int k = 0; k < 12; ++k) ps[u][k] = pose_l[hl][k];
+            }
+            int cu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int k0 = tid; k0 < d.n; k0 += 1024) {   // four matches per thread in flight
+                float x[4][3], y[4][3];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const int64_t gi = d.pt_off + min(k0 + 256 * m, d.n - 1);
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        x[m][f] = w.src[3 * gi + f];
+                        y[m][f] = w.dst[3 * gi + f];
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const bool in = k0 + 256 * m < d.n;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        cu[u] += in && residual2(ps[u], x[m][0], x[m][1], x[m][2], y[m][0], y[m][1], y[m][2]) <= th2;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = wave_total(cu[u]);
+                if (lane == 0 && t && h0 + u < nloc) atomicAdd(&tot_l[h0 + u], t);
+            }
         }
-        // Device-scope integer atomics are performed at the device's coherence point, so once every
-        // thread has seen its own additions acknowledged (vmcnt 0) and the workgroup has met, the
-        // ticket below is ordered after all of them; the last workgroup reads IN with cache-bypassing
-        // atomic loads. (A full __threadfence here would write back and invalidate the XCD's L2 on
-        // every item.)
+        __syncthreads();
+        uint64_t key = 0;
+        int nv = 0;
+        if (tid < nloc) {
+            const int lp = tid / w.k2, s2 = tid - lp * w.k2, p = g * ppw + lp;
+            if (p < w.k1) {
+                const int64_t h = (int64_t)s2 * w.k1 + p, slot = (int64_t)b * w.h_cap + h;
+                __hip_atomic_store(&w.inl[slot], valid_l[tid] ? tot_l[tid] : -1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) store_agent(w.poses + slot * 12 + k, pose_l[tid][k]);
+                if (valid_l[tid]) {
+                    key = ((uint64_t)(tot_l[tid] + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
+                    nv = 1;
+                }
+            }
+        }
+        // this item's best hypothesis and valid count, folded into the pair's state (lowest h on ties)
+        key = wave_max_u64(key);
+        nv = wave_total(nv);
+        if (lane == 0 && wv < (nloc + 63) / 64) {
+            if (key) atomicMax(reinterpret_cast<unsigned long long *>(&w.state[b].best), (unsigned long long)key);
+            if (nv) atomicAdd(&w.state[b].n_valid, nv);
+        }
+        // every store and atomic of this item has been acknowledged before the ticket; the last
+        // workgroup of the pair reads the state and the best pose with device-scope loads
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (tid == 0) {
-            const int t = atomicAdd(&w.state[b].done, 1);
-            last = t == pre[b + 1] - pre[b] - 1;
-        }
+        if (tid == 0) last = atomicAdd(&w.state[b].done, 1) == ipp - 1;
         __syncthreads();
         if (last) select_pair(w, b);
-        __syncthreads();   // pts and last are the next item's
+        __syncthreads();   // LDS is the next item's
     }
 }
 
 }  // namespace
 
-hipError_t launch_cliques(const Work &w, int B, hipStream_t s)
+hipError_t setup_hyp_kernels()
 {
-    const int total = B * w.k1;
-    const int grid = min((total + 3) / 4, 4096);
-    if (w.k2 <= 2) hipLaunchKernelGGL(k_cliques<2>, dim3(grid), dim3(256), 0, s, w, total);
-    else hipLaunchKernelGGL(k_cliques<TR_MAX_K2>, dim3(grid), dim3(256), 0, s, w, total);
-    return hipGetLastError();
+    return hipSuccess;
 }
 
-hipError_t launch_score(const Work &w, int grid, hipStream_t s)
+hipError_t launch_hyp(const Work &w, int B, int num_cus, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_score, dim3(grid), dim3(256), 0, s, w);
+    const int ppw = B == 1 ? 4 : 16;   // batches: more pivots per workgroup, fewer passes over each pair's matches
+    const int total = B * ((w.k1 + ppw - 1) / ppw);
+    const int grid = min(total, num_cus * 4);
+    if (w.k2 <= 2) hipLaunchKernelGGL(k_hyp<2>, dim3(grid), dim3(256), 0, s, w, B, ppw);
+    else hipLaunchKernelGGL(k_hyp<TR_MAX_K2>, dim3(grid), dim3(256), 0, s, w, B, ppw);
     return hipGetLastError();
 }
 

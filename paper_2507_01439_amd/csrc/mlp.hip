@@ -77,12 +77,12 @@ __device__ float forward(const MlpLds &L, const float (&x)[19])
 // then to bfloat16.
 __global__ void __launch_bounds__(256) k_features(Work w, uint16_t *packed)
 {
-    const int total = w.plan->total[kPrep], B = w.plan->B;
-    const int32_t *pre = w.pre + kPrep * w.pre_stride;
+    const int total = stage_total(w, kPrep);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
-        const int i = (item - pre[b]) * kPrepRows + threadIdx.x;
+        int local;
+        const int b = stage_pair(w, kPrep, item, local);
+        const PairDesc d = pair_desc(w, b);
+        const int i = local * kPrepRows + threadIdx.x;
         if (i >= d.n) continue;
         const int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
         const double n1 = (double)(d.n - 1), n = (double)d.n;
@@ -102,12 +102,12 @@ __global__ void __launch_bounds__(256) k_mlp_rows(Work w, const uint16_t *wbf16,
     __shared__ MlpLds L;
     load_params(L, wbf16, w32);
     __syncthreads();
-    const int total = w.plan->total[kPrep], B = w.plan->B;
-    const int32_t *pre = w.pre + kPrep * w.pre_stride;
+    const int total = stage_total(w, kPrep);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
-        const PairDesc d = w.pairs[b];
-        const int i = (item - pre[b]) * kPrepRows + threadIdx.x;
+        int local;
+        const int b = stage_pair(w, kPrep, item, local);
+        const PairDesc d = pair_desc(w, b);
+        const int i = local * kPrepRows + threadIdx.x;
         bool bad = false;
         if (i < d.n) {
             const uint16_t *f = w.feat + ((int64_t)b * w.max_n + i) * 19;
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(1024) k_reorder(Work w)
 {
     extern __shared__ uint64_t keys[];
     const int b = blockIdx.x;
-    const PairDesc d = w.pairs[b];
+    const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv;
     const bool fb = w.state[b].fallback != 0;
     int P = 64;

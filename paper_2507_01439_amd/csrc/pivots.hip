@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     __shared__ int64_t lds[17];
     __shared__ int32_t res[3];
     const int b = blockIdx.x;
-    const PairDesc d = w.pairs[b];
+    const PairDesc d = pair_desc(w, b);
     const int64_t K = d.kpiv;
     if (K <= 0) return;
     const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.max_n;
@@ -213,15 +213,15 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
     __shared__ uint64_t buf[kCollectCap];
     __shared__ int32_t nbuf, base;
     __shared__ int32_t part[4][2];
-    const int total = w.plan->total[kRowBlk], B = w.plan->B;
-    const int32_t *pre = w.pre + kRowBlk * w.pre_stride;
+    const int total = stage_total(w, kRowBlk);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
+        int blk;
+        const int b = stage_pair(w, kRowBlk, item, blk);
         const PairState st = w.state[b];
-        const PairDesc d = w.pairs[b];
+        const PairDesc d = pair_desc(w, b);
         if (d.kpiv <= 0) continue;   // same for the whole workgroup
-        const int blk = item - pre[b], alpha = st.alpha, c1 = (d.n + 7) >> 3;
+        const int alpha = st.alpha, c1 = (d.n + 7) >> 3;
         const int i = blk * kRowsPerItem + wv;
         const int rm = i < d.n ? w.rowmax[(int64_t)b * w.max_n + i] : 0;
         const bool live = i < d.n && !(alpha > 0 && rm < alpha);
@@ -330,15 +330,14 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
 {
     __shared__ int64_t lds[17];
     __shared__ int32_t rowpre[kRowsPerItem][2];
-    const int total = w.plan->total[kRowBlk], B = w.plan->B;
-    const int32_t *pre = w.pre + kRowBlk * w.pre_stride;
+    const int total = stage_total(w, kRowBlk);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = find_pair(pre, B, item);
+        int blk;
+        const int b = stage_pair(w, kRowBlk, item, blk);
         const PairState st = w.state[b];
-        const PairDesc d = w.pairs[b];
+        const PairDesc d = pair_desc(w, b);
         if (st.fast || d.kpiv <= 0) continue;   // same for the whole workgroup
-        const int blk = item - pre[b];
         // counts of all earlier blocks of this pair
         int64_t pg = 0, pe = 0;
         for (int k = threadIdx.x; k < blk; k += 256) {
@@ -434,7 +433,7 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     extern __shared__ uint64_t keys[];
     __shared__ int32_t part[4][64];
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
-    const PairDesc d = w.pairs[b];
+    const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int NC = K > 0 ? min(w.state[b].ncand, w.pool_cap) : 0;   // keys ranked; the first K are kept
     int32_t *out = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
@@ -442,6 +441,33 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     const uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
     const int K16 = (NC + 15) & ~15;   // padded with keys larger than any real one
     for (int k = tid; k < K16; k += 256) keys[k] = k < NC ? cand[k] : ~0ull;
+    if (g == 0) {   // the pair's first workgroup: boundary pairs, edges and non-finite input over its tiles
+        const int t0 = stage_first(w, kCompat, b), t1 = t0 + stage_count(w, kCompat, b);
+        int c[3] = {0, 0, 0};
+        for (int tb = t0 + tid; tb < t1; tb += 256 * 8) {   // eight tiles per thread loaded before any is added
+            int v[8][3];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = tb + 256 * u;
+#pragma unroll
+                for (int f = 0; f < 3; ++f) v[u][f] = t < t1 ? w.cnt_part[3 * (int64_t)t + f] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) c[f] += v[u][f];
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) c[f] += __shfl_xor(c[f], o, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(&w.state[b].n_boundary, c[0]);
+            atomicAdd(&w.state[b].n_edges, c[1]);
+            if (c[2]) atomicOr(&w.state[b].nonfinite, 1);
+        }
+    }
     __syncthreads();
     const int p = g * 64 + lane;
     const uint64_t mine = p < NC ? keys[p] : 0;

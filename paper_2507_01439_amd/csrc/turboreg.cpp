@@ -118,6 +118,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.plan = h->plan;
     w.pre = h->pre;
     w.pre_stride = h->pre_stride;
+    w.n1 = 0;
     w.max_n = h->max_n;
     w.k1 = p.k1;
     w.k2 = p.k2;
@@ -187,10 +188,10 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
         if (x != hipSuccess && e == hipSuccess) e = x;
     };
     mark(TR_STAGE_PLAN);
-    chk(launch_plan(w, offsets, n_single, B, max_n, h->pairs, h->state, h->plan, h->pre, s));
+    if (!w.n1) chk(launch_plan(w, offsets, n_single, B, max_n, h->pairs, h->state, h->plan, h->pre, s));
     if (w.learned) chk(launch_prep_learned(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
     mark(TR_STAGE_COMPAT);
-    chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 8), s));
+    chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 4), s));   // one round of resident workgroups
     mark(TR_STAGE_SC2);
     {
         // one workgroup per CU; the kernel splits its items into 8 equal ranges, one per XCD
@@ -210,11 +211,10 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
         chk(launch_learned_order(w, h->mlp, B, g, s));
     }
     mark(TR_STAGE_CLIQUES);
-    chk(launch_cliques(w, B, s));   // also fits each clique's pose (the Kabsch stage)
+    // cliques, their poses, their inlier counts and (last workgroup per pair) the selection
+    chk(launch_hyp(w, B, h->num_cus, s));
     mark(TR_STAGE_KABSCH);
     mark(TR_STAGE_SCORE);
-    const int64_t score_items = (int64_t)B * ((w.H + kScoreHyp - 1) / kScoreHyp) * ((max_n + kScorePts - 1) / kScorePts);
-    chk(launch_score(w, grid_cap(h, score_items, 8), s));   // its last workgroup per pair selects the result
     mark(TR_STAGE_SELECT);
     mark(TR_NUM_STAGES);
     if (e != hipSuccess) {
@@ -334,7 +334,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->rowmax, B * max_n));
     {
         const size_t nb64 = h->npad_max / kCompatTile;
-        A(alloc(h, &h->cnt_part, B * nb64 * (nb64 + 1) / 2 * 2));
+        A(alloc(h, &h->cnt_part, B * nb64 * (nb64 + 1) / 2 * 3));   // boundary pairs, edges, non-finite flag
     }
     A(alloc(h, &h->rowcnt, B * max_n * 2));
     A(alloc(h, &h->blkcnt, B * h->nblk_stride * 2));
@@ -353,6 +353,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(setup_graph_kernels());
     A(setup_pivot_kernels());
     A(setup_mlp_kernels());
+    A(setup_hyp_kernels());
     if (e != hipSuccess) {
         std::fprintf(stderr, "turboreg: tr_create failed: %s\n", hipGetErrorString(e));
         release(h);
@@ -384,6 +385,7 @@ tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t 
     const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
     const int pmode = profile_mode(p->flags);
     Work w = make_work(h, src, dst, *p, out_dev, mask_dev, learned, 1, n);
+    w.n1 = n;   // the kernels derive this pair's plan from n (no planner launch)
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t *ev = nullptr;
     if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
@@ -472,9 +474,10 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
     if (!h || !h->last_valid || pair < 0 || pair >= h->last_B) return TR_ERR_INVALID_ARG;
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     if (hipStreamSynchronize(h->last_stream) != hipSuccess) return TR_ERR_HIP;
-    PairDesc d;
-    if (hipMemcpy(&d, h->pairs + pair, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return TR_ERR_HIP;
     const Work &w = h->last;
+    PairDesc d;
+    if (w.n1) d = pair_desc_of(w.n1, 0, 0, w.pool);   // single-pair calls keep no device descriptor
+    else if (hipMemcpy(&d, h->pairs + pair, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return TR_ERR_HIP;
     const size_t n = d.n;
     size_t need = 0;
     const void *srcp = nullptr;
