@@ -97,45 +97,80 @@ __global__ void __launch_bounds__(256) k_features(Work w, uint16_t *packed)
 
 // ---------------------------------------------------------------- inference + reorder
 
-__global__ void __launch_bounds__(256) k_mlp_rows(Work w, const uint16_t *wbf16, const float *w32)
+__device__ __forceinline__ float lane_f(float v, int k)
 {
-    __shared__ MlpLds L;
-    load_params(L, wbf16, w32);
-    __syncthreads();
-    const int total = stage_total(w, kPrep);
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int local;
-        const int b = stage_pair(w, kPrep, item, local);
-        const PairDesc d = pair_desc(w, b);
-        const int i = local * kPrepRows + threadIdx.x;
-        bool bad = false;
-        if (i < d.n) {
-            const uint16_t *f = w.feat + ((int64_t)b * w.max_n + i) * 19;
-            float x[19];
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// Features and score of one match per wave (learned pivots). Lane k < 19
+// forms feature k from the integer accumulators (as k_features) and writes
+// it; lane o holds hidden unit o's weights in registers, so each layer is one
+// multiply-add chain per lane over inputs broadcast with v_readlane, in the
+// same order as the one-thread forward pass. The workgroup loads the weights
+// once and walks row blocks of kRowsPerItem (one row per wave).
+__global__ void __launch_bounds__(256) k_learned_rows(Work w, const uint16_t *wbf16, const float *w32)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float w1[19], w2[64];
 #pragma unroll
-            for (int k = 0; k < 19; ++k) x[k] = bf2f(f[k]);
-            const float s = forward(L, x);
-            w.scores[(int64_t)b * w.max_n + i] = s;
-            bad = !isfinite(s);
+    for (int k = 0; k < 19; ++k) w1[k] = bf2f(wbf16[kW1 + 19 * lane + k]);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) w2[k] = bf2f(wbf16[kW2 + 64 * lane + k]);
+    const float b1 = w32[kB1 + lane], b2 = w32[kB2 + lane], w3 = bf2f(wbf16[kW3 + lane]), b3 = w32[kB3];
+    const int total = stage_total(w, kRowBlk);
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        int blk;
+        const int b = stage_pair(w, kRowBlk, item, blk);
+        const PairDesc d = pair_desc(w, b);
+        const int i = blk * kRowsPerItem + wv;
+        if (i >= d.n) continue;   // wave-uniform
+        const int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+        const double n1 = (double)(d.n - 1), n = (double)d.n;
+        uint16_t fb = 0;
+        if (lane < 19) {
+            const int v = rs[lane];
+            fb = f2bf((float)((double)v / (lane == 0 ? n1 : lane == 1 ? n1 * n : lane == 2 ? n : n1)));
+            w.feat[((int64_t)b * w.max_n + i) * 19 + lane] = fb;
         }
-        if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&w.state[b].fallback, 1);
+        float acc = b1;
+#pragma unroll
+        for (int k = 0; k < 19; ++k)
+            acc = __builtin_fmaf(w1[k], bf2f((uint16_t)__builtin_amdgcn_readlane((int)fb, k)), acc);
+        const float a1 = bfround(gelu(acc));
+        acc = b2;
+#pragma unroll
+        for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(w2[k], lane_f(a1, k), acc);
+        const float a2 = bfround(gelu(acc));
+        float s = b3;
+#pragma unroll
+        for (int o = 0; o < 64; ++o) s = __builtin_fmaf(lane_f(w3, o), lane_f(a2, o), s);
+        if (lane == 0) {
+            w.scores[(int64_t)b * w.max_n + i] = s;
+            if (!isfinite(s)) atomicOr(&w.state[b].fallback, 1);
+        }
     }
 }
 
 // Order the pool of plain pivots by e = s_i + s_j (desc), ties by plain rank,
 // keep the first K1. Non-finite scores anywhere in the pair: keep plain order.
-__global__ void __launch_bounds__(1024) k_reorder(Work w)
+// Keys are distinct (the plain rank is part of each), so a key's new position
+// is the number of smaller keys: each 256-thread workgroup rebuilds the
+// pair's K keys in LDS and ranks 64 of them, a quarter of the list per wave,
+// eight 16-byte broadcast reads in flight.
+__global__ void __launch_bounds__(256) k_reorder(Work w, int blocks_per_pair)
 {
     extern __shared__ uint64_t keys[];
-    const int b = blockIdx.x;
+    __shared__ int32_t part[4][64];
+    const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv;
+    if (g * 64 >= max(K, w.k1)) return;
     const bool fb = w.state[b].fallback != 0;
-    int P = 64;
-    while (P < K) P <<= 1;
     const int32_t *pl = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
     const float *sc = w.scores + (int64_t)b * w.max_n;
-    for (int r = threadIdx.x; r < P; r += 1024) {
+    const int K16 = (K + 15) & ~15;
+    for (int r = tid; r < K16; r += 256) {
         uint64_t k = ~0ull;
         if (r < K) {
             uint32_t hi = 0;
@@ -150,19 +185,36 @@ __global__ void __launch_bounds__(1024) k_reorder(Work w)
         keys[r] = k;
     }
     __syncthreads();
-    bitonic_sort_lds(keys, P);
-    int32_t *out = w.pivots + (int64_t)b * w.piv_stride * 3;
-    for (int p = threadIdx.x; p < w.k1; p += 1024) {
-        if (p < K) {
-            const int r = (int)(uint32_t)keys[p];
-            out[3 * p] = pl[3 * r];
-            out[3 * p + 1] = pl[3 * r + 1];
-            out[3 * p + 2] = pl[3 * r + 2];
-        } else {
-            out[3 * p] = -1;
-            out[3 * p + 1] = -1;
-            out[3 * p + 2] = 0;
+    const int p = g * 64 + lane;
+    const uint64_t mine = p < K ? keys[p] : 0;
+    const int per = ((K16 / 16 + 3) / 4) * 16;
+    const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
+    int rk = 0;
+    for (int q = q0; q < q1; q += 16) {
+        uint4 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const uint4 *>(&keys[q + 2 * u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            rk += (((uint64_t)a[u].y << 32) | a[u].x) < mine;
+            rk += (((uint64_t)a[u].w << 32) | a[u].z) < mine;
         }
+    }
+    part[wv][lane] = rk;
+    __syncthreads();
+    if (wv != 0) return;
+    rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    int32_t *out = w.pivots + (int64_t)b * w.piv_stride * 3;
+    if (p < K && rk < w.k1) {
+        const int r = (int)(uint32_t)mine;
+        out[3 * rk] = pl[3 * r];
+        out[3 * rk + 1] = pl[3 * r + 1];
+        out[3 * rk + 2] = pl[3 * r + 2];
+    }
+    if (p >= K && p < w.k1) {   // slots past the pair's pivots
+        out[3 * p] = -1;
+        out[3 * p + 1] = -1;
+        out[3 * p + 2] = 0;
     }
 }
 
@@ -471,10 +523,10 @@ hipError_t launch_features(const Work &w, uint16_t *packed, int grid, hipStream_
 
 hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mlp_rows, dim3(grid), dim3(256), 0, st, w, mlp.wbf16, mlp.w32);
-    int P = 64;
-    while (P < w.pool) P <<= 1;
-    hipLaunchKernelGGL(k_reorder, dim3(B), dim3(1024), (size_t)P * sizeof(uint64_t), st, w);
+    hipLaunchKernelGGL(k_learned_rows, dim3(grid), dim3(256), 0, st, w, mlp.wbf16, mlp.w32);
+    const int bpp = (max(w.pool, w.k1) + 63) / 64;
+    hipLaunchKernelGGL(k_reorder, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), st, w,
+                       bpp);
     return hipGetLastError();
 }
 

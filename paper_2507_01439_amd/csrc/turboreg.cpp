@@ -206,9 +206,8 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
     mark(TR_STAGE_LEARNED);
     if (w.learned) {
-        const int g = grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8);
-        chk(launch_features(w, nullptr, g, s));
-        chk(launch_learned_order(w, h->mlp, B, g, s));
+        // features and scores (one match per wave), then the reorder of the pool
+        chk(launch_learned_order(w, h->mlp, B, grid_cap(h, rows_items, 8), s));
     }
     mark(TR_STAGE_CLIQUES);
     // cliques, their poses, their inlier counts and (last workgroup per pair) the selection
