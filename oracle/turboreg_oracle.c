@@ -628,6 +628,9 @@ static int lkey_cmp(const void *a, const void *b)
     return x->r < y->r ? -1 : (x->r > y->r);
 }
 
+/* Learned reorder of the plain pool: key e = s_i + s_j in float32, descending, ties by plain
+ * rank; a non-finite score at either end of any valid pool pivot keeps the plain order and
+ * reports the fallback (the scorer's output cannot be trusted for that pair). */
 int tro_pivots_learned(const int32_t *P_plain, int32_t pool, const float *s, int32_t k1,
                        int32_t *P)
 {
@@ -640,7 +643,7 @@ int tro_pivots_learned(const int32_t *P_plain, int32_t pool, const float *s, int
     for (int32_t r = 0; r < valid; ++r) {
         k[r].e = s[P_plain[3 * r]] + s[P_plain[3 * r + 1]];
         k[r].r = r;
-        if (isnan(k[r].e)) fallback = 1;
+        if (!isfinite(s[P_plain[3 * r]]) || !isfinite(s[P_plain[3 * r + 1]])) fallback = 1;
     }
     if (!fallback) qsort(k, (size_t)valid, sizeof(lkey_t), lkey_cmp);
     for (int32_t p = 0; p < k1; ++p) {

@@ -86,6 +86,8 @@ struct Work {
     int32_t *inl;             // max_batch x h_cap
     int32_t h_cap;
     int32_t *rowstat;         // max_batch x max_n x 20 feature accumulators (learned mode)
+    int32_t *mark;            // max_batch x max_n: row claimed by a candidate-feature workgroup
+    int32_t feat_all;         // learned features for every match (training) instead of the pool's
     uint16_t *feat;           // max_batch x max_n x 19 bfloat16 features
     float *scores;            // max_batch x max_n learned scores
     tr_result *out;
@@ -95,6 +97,17 @@ struct Work {
 
 
 // Largest b in [0, B) with pre[b] <= item (pre is non-decreasing, pre[0] = 0).
+// Length of a difference vector in float32: first square rounded, the other
+// two fused, then the correctly rounded square root (the order is part of the
+// bit-exact contract of C).
+__device__ __forceinline__ float length32(float ax, float ay, float az)
+{
+    float s = ax * ax;
+    s = __builtin_fmaf(ay, ay, s);
+    s = __builtin_fmaf(az, az, s);
+    return __builtin_sqrtf(s);
+}
+
 __device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)
 {
     int lo = 0, hi = B - 1;

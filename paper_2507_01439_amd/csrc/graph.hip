@@ -158,16 +158,6 @@ __global__ void __launch_bounds__(256) k_prep_learned(Work w)
 
 // ---------------------------------------------------------------- Eq. 1
 
-// Length of a difference vector in float32: first square rounded, the other
-// two fused, then the correctly rounded square root (the order is part of the
-// bit-exact contract of C).
-__device__ __forceinline__ float length32(float ax, float ay, float az)
-{
-    float s = ax * ax;
-    s = __builtin_fmaf(ay, ay, s);
-    s = __builtin_fmaf(az, az, s);
-    return __builtin_sqrtf(s);
-}
 
 constexpr int kNibStride = 32;    // LDS row stride of a packed 64-column tile (two entries per byte)
 
@@ -250,7 +240,15 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
                 const int i = bi * kCompatTile + (k & 63);
                 if (i < d.n) w.ghist[((int64_t)b * kHistGroups + (k >> 6)) * w.max_n + i] = 0;
             }
-            if (tid < 64 && bi * kCompatTile + tid < d.n) w.rowmax[(int64_t)b * w.max_n + bi * kCompatTile + tid] = 0;
+            if (tid < 64 && bi * kCompatTile + tid < d.n) {
+                const int64_t ri = (int64_t)b * w.max_n + bi * kCompatTile + tid;
+                w.rowmax[ri] = 0;
+                if (!LEARNED && w.learned) {   // pool-feature mode: the SC2 row statistics and the row marks
+                    w.rowstat[ri * 20 + 1] = 0;
+                    w.rowstat[ri * 20 + 2] = 0;
+                    w.mark[ri] = 0;
+                }
+            }
         }
         if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) { hrow[k / 17][k % 17] = 0; hcol[k / 17][k % 17] = 0; }
@@ -674,7 +672,7 @@ hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_compat(const Work &w, int grid, hipStream_t s)
 {
-    if (w.learned) hipLaunchKernelGGL(k_compat<true>, dim3(grid), dim3(256), 0, s, w);
+    if (w.learned && w.feat_all) hipLaunchKernelGGL(k_compat<true>, dim3(grid), dim3(256), 0, s, w);
     else hipLaunchKernelGGL(k_compat<false>, dim3(grid), dim3(256), 0, s, w);
     return hipGetLastError();
 }

@@ -102,36 +102,37 @@ __device__ __forceinline__ float lane_f(float v, int k)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
-// Features and score of one match per wave (learned pivots). Lane k < 19
-// forms feature k from the integer accumulators (as k_features) and writes
-// it; lane o holds hidden unit o's weights in registers, so each layer is one
-// multiply-add chain per lane over inputs broadcast with v_readlane, in the
-// same order as the one-thread forward pass. The workgroup loads the weights
-// once and walks row blocks of kRowsPerItem (one row per wave).
-__global__ void __launch_bounds__(256) k_learned_rows(Work w, const uint16_t *wbf16, const float *w32)
+// Sum over the 64 lanes (DPP), valid in every lane.
+__device__ __forceinline__ int wave_total(int v)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    float w1[19], w2[64];
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Score of one match by a whole wave: lane o holds hidden unit o's weights,
+// each layer is one multiply-add chain per lane over inputs broadcast with
+// v_readlane, in the same order as the one-thread forward pass. fb: lane k <
+// 19 holds feature k (bfloat16 bits).
+struct WaveMlp {
+    float w1[19], w2[64], b1, b2, w3, b3;
+    __device__ void load(const uint16_t *wbf16, const float *w32, int lane)
+    {
 #pragma unroll
-    for (int k = 0; k < 19; ++k) w1[k] = bf2f(wbf16[kW1 + 19 * lane + k]);
+        for (int k = 0; k < 19; ++k) w1[k] = bf2f(wbf16[kW1 + 19 * lane + k]);
 #pragma unroll
-    for (int k = 0; k < 64; ++k) w2[k] = bf2f(wbf16[kW2 + 64 * lane + k]);
-    const float b1 = w32[kB1 + lane], b2 = w32[kB2 + lane], w3 = bf2f(wbf16[kW3 + lane]), b3 = w32[kB3];
-    const int total = stage_total(w, kRowBlk);
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int blk;
-        const int b = stage_pair(w, kRowBlk, item, blk);
-        const PairDesc d = pair_desc(w, b);
-        const int i = blk * kRowsPerItem + wv;
-        if (i >= d.n) continue;   // wave-uniform
-        const int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
-        const double n1 = (double)(d.n - 1), n = (double)d.n;
-        uint16_t fb = 0;
-        if (lane < 19) {
-            const int v = rs[lane];
-            fb = f2bf((float)((double)v / (lane == 0 ? n1 : lane == 1 ? n1 * n : lane == 2 ? n : n1)));
-            w.feat[((int64_t)b * w.max_n + i) * 19 + lane] = fb;
-        }
+        for (int k = 0; k < 64; ++k) w2[k] = bf2f(wbf16[kW2 + 64 * lane + k]);
+        b1 = w32[kB1 + lane];
+        b2 = w32[kB2 + lane];
+        w3 = bf2f(wbf16[kW3 + lane]);
+        b3 = w32[kB3];
+    }
+    __device__ float score(uint16_t fb) const
+    {
         float acc = b1;
 #pragma unroll
         for (int k = 0; k < 19; ++k)
@@ -144,10 +145,114 @@ __global__ void __launch_bounds__(256) k_learned_rows(Work w, const uint16_t *wb
         float s = b3;
 #pragma unroll
         for (int o = 0; o < 64; ++o) s = __builtin_fmaf(lane_f(w3, o), lane_f(a2, o), s);
-        if (lane == 0) {
-            w.scores[(int64_t)b * w.max_n + i] = s;
-            if (!isfinite(s)) atomicOr(&w.state[b].fallback, 1);
+        return s;
+    }
+};
+
+// Feature k of a match (lane k < 19) from its integer accumulators, as k_features.
+__device__ __forceinline__ uint16_t feature_bits(const int32_t *rs, int k, int n)
+{
+    const double n1 = (double)(n - 1), nn = (double)n;
+    return f2bf((float)((double)rs[k] / (k == 0 ? n1 : k == 1 ? n1 * nn : k == 2 ? nn : n1)));
+}
+
+// Features and score of every match the reorder needs: the endpoints of the
+// pair's plain pivot pool. Each distinct row is claimed by one workgroup
+// (compare-and-swap on its mark), which evaluates delta_ij for all j != i
+// exactly as the compatibility kernel does (same operation order, correctly
+// rounded square roots) to count the degree and the 16-bin delta histogram;
+// the SC2 row sum and maximum come from the SC2 epilogue. Wave 0 then scores
+// the match. Matches outside the pool get no features and no score.
+__global__ void __launch_bounds__(256) k_cand_rows(Work w, int B, const uint16_t *wbf16, const float *w32)
+{
+    __shared__ int32_t red[4][17];
+    __shared__ int32_t own;
+    __shared__ int32_t rs_l[20];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    WaveMlp mlp;
+    if (wv == 0) mlp.load(wbf16, w32, lane);
+    const float tau = w.tau, q = tau * 0.25f;
+    float edge[16];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) edge[k] = (float)k * q;   // bin edges as the compatibility kernel forms them
+    const int per_pair = 2 * w.pool, total = B * per_pair;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int b = item / per_pair, e = item - b * per_pair;
+        const PairDesc d = pair_desc(w, b);
+        if ((e >> 1) >= d.kpiv) continue;   // same for the whole workgroup
+        const int i = w.pivots_plain[((int64_t)b * w.pool_cap + (e >> 1)) * 3 + (e & 1)];
+        if (i < 0 || i >= d.n) continue;
+        if (tid == 0) own = atomicCAS(&w.mark[(int64_t)b * w.max_n + i], 0, 1) == 0;
+        __syncthreads();
+        const bool mine = own;
+        __syncthreads();
+        if (!mine) continue;
+        const int64_t gi = d.pt_off + i;
+        const float xi0 = w.src[3 * gi], xi1 = w.src[3 * gi + 1], xi2 = w.src[3 * gi + 2];
+        const float yi0 = w.dst[3 * gi], yi1 = w.dst[3 * gi + 1], yi2 = w.dst[3 * gi + 2];
+        uint32_t cw[4] = {0, 0, 0, 0};   // 16 bins, 8 bits each (at most ceil(32767/256) per thread)
+        int deg = 0;
+        constexpr int kU = 8;             // point loads in flight per thread
+        for (int j0 = tid; j0 < d.n; j0 += 256 * kU) {
+            float p[kU][6];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t gj = d.pt_off + min(j0 + 256 * u, d.n - 1);
+                p[u][0] = w.src[3 * gj]; p[u][1] = w.src[3 * gj + 1]; p[u][2] = w.src[3 * gj + 2];
+                p[u][3] = w.dst[3 * gj]; p[u][4] = w.dst[3 * gj + 1]; p[u][5] = w.dst[3 * gj + 2];
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = j0 + 256 * u;
+                const float lx = length32(xi0 - p[u][0], xi1 - p[u][1], xi2 - p[u][2]);
+                const float ly = length32(yi0 - p[u][3], yi1 - p[u][4], yi2 - p[u][5]);
+                const float dl = __builtin_fabsf(lx - ly);
+                const bool in = j < d.n && j != i;
+                deg += in && dl <= tau;
+                int bin = 0;
+#pragma unroll
+                for (int k = 1; k < 16; ++k) bin += dl >= edge[k];
+                const uint32_t inc = in ? 1u << (8 * (bin & 3)) : 0u;
+                cw[0] += (bin >> 2) == 0 ? inc : 0u;
+                cw[1] += (bin >> 2) == 1 ? inc : 0u;
+                cw[2] += (bin >> 2) == 2 ? inc : 0u;
+                cw[3] += (bin >> 2) == 3 ? inc : 0u;
+            }
         }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int t = wave_total((int)((cw[k >> 2] >> (8 * (k & 3))) & 0xFFu));
+            if (lane == 0) red[wv][1 + k] = t;
+        }
+        deg = wave_total(deg);
+        if (lane == 0) red[wv][0] = deg;
+        __syncthreads();
+        int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+        if (tid < 19) {
+            int v;
+            if (tid == 0 || tid >= 3) {   // degree, histogram bins 0..15
+                const int f = tid == 0 ? 0 : tid - 2;
+                v = red[0][f] + red[1][f] + red[2][f] + red[3][f];
+                rs[tid] = v;
+            } else {
+                v = rs[tid];   // SC2 row sum / maximum
+            }
+            rs_l[tid] = v;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            uint16_t fb = 0;
+            if (lane < 19) {
+                fb = feature_bits(rs_l, lane, d.n);
+                w.feat[((int64_t)b * w.max_n + i) * 19 + lane] = fb;
+            }
+            const float sc = mlp.score(fb);
+            if (lane == 0) {
+                w.scores[(int64_t)b * w.max_n + i] = sc;
+                if (!isfinite(sc)) atomicOr(&w.state[b].fallback, 1);
+            }
+        }
+        __syncthreads();   // red and rs_l are the next item's
     }
 }
 
@@ -523,7 +628,8 @@ hipError_t launch_features(const Work &w, uint16_t *packed, int grid, hipStream_
 
 hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_learned_rows, dim3(grid), dim3(256), 0, st, w, mlp.wbf16, mlp.w32);
+    const int cand = B * 2 * w.pool;
+    hipLaunchKernelGGL(k_cand_rows, dim3(min(cand, grid * 4)), dim3(256), 0, st, w, B, mlp.wbf16, mlp.w32);
     const int bpp = (max(w.pool, w.k1) + 63) / 64;
     hipLaunchKernelGGL(k_reorder, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), st, w,
                        bpp);

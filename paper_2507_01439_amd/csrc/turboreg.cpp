@@ -48,7 +48,7 @@ struct tr_handle {
     uint64_t *cand = nullptr, *rowseg = nullptr;
     int32_t *pivots_plain = nullptr, *pivots = nullptr, *cliques = nullptr, *inl = nullptr;
     float *poses = nullptr;
-    int32_t *rowstat = nullptr;
+    int32_t *rowstat = nullptr, *mark = nullptr;
     uint16_t *feat = nullptr;
     float *scores = nullptr;
     tr_result *scratch_out = nullptr;   // results of feature-only passes
@@ -146,6 +146,8 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.inl = h->inl;
     w.h_cap = h->h_cap;
     w.rowstat = h->rowstat;
+    w.mark = h->mark;
+    w.feat_all = 0;
     w.feat = h->feat;
     w.scores = h->scores;
     w.out = out;
@@ -189,7 +191,8 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     };
     mark(TR_STAGE_PLAN);
     if (!w.n1) chk(launch_plan(w, offsets, n_single, B, max_n, h->pairs, h->state, h->plan, h->pre, s));
-    if (w.learned) chk(launch_prep_learned(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
+    if (w.learned && w.feat_all)
+        chk(launch_prep_learned(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
     mark(TR_STAGE_COMPAT);
     chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 4), s));   // one round of resident workgroups
     mark(TR_STAGE_SC2);
@@ -206,8 +209,8 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
     mark(TR_STAGE_LEARNED);
     if (w.learned) {
-        // features and scores (one match per wave), then the reorder of the pool
-        chk(launch_learned_order(w, h->mlp, B, grid_cap(h, rows_items, 8), s));
+        // features and scores of the pool's endpoints, then the reorder of the pool
+        chk(launch_learned_order(w, h->mlp, B, h->num_cus, s));
     }
     mark(TR_STAGE_CLIQUES);
     // cliques, their poses, their inlier counts and (last workgroup per pair) the selection
@@ -345,6 +348,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->poses, B * h->h_cap * 12));
     A(alloc(h, &h->inl, B * h->h_cap));
     A(alloc(h, &h->rowstat, B * max_n * 20));
+    A(alloc(h, &h->mark, B * max_n));
     A(alloc(h, &h->feat, B * max_n * 19));
     A(alloc(h, &h->scores, B * max_n));
     A(alloc(h, &h->scratch_out, B));
@@ -458,6 +462,7 @@ tr_status tr_features_batch(tr_handle *h, const float *src, const float *dst, co
     q.k2 = 1;
     q.pool_factor = 1;
     Work w = make_work(h, src, dst, q, h->scratch_out, nullptr, true, B, max_n);
+    w.feat_all = 1;   // every match's features (training data)
     hipStream_t s = static_cast<hipStream_t>(stream);
     tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, true, s);
     if (st != TR_OK) return st;

@@ -522,6 +522,14 @@ def test_learned_pivots_order_and_fallback():
     s3[3] = np.nan
     out, fb = oracle.pivots_learned(P, s3, 2)
     assert fb and out[:, :2].tolist() == [[0, 1], [2, 3]]
+    s4 = s.copy()
+    s4[6] = np.inf                                                     # finite partner: key is inf, still a fallback
+    out, fb = oracle.pivots_learned(P, s4, 2)
+    assert fb and out[:, :2].tolist() == [[0, 1], [2, 3]]
+    P5 = P.copy()
+    P5[3] = [-1, -1, 0]                                                # rows past the valid pool are never read
+    out, fb = oracle.pivots_learned(P5, np.where(np.arange(8) >= 6, np.nan, s).astype(np.float32), 3)
+    assert not fb and out[:, :2].tolist() == [[4, 5], [2, 3], [0, 1]]
 
 
 @pytest.mark.parametrize("seed", [0, 1])
