@@ -114,145 +114,225 @@ __device__ __forceinline__ int wave_total(int v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
-// Score of one match by a whole wave: lane o holds hidden unit o's weights,
-// each layer is one multiply-add chain per lane over inputs broadcast with
-// v_readlane, in the same order as the one-thread forward pass. fb: lane k <
-// 19 holds feature k (bfloat16 bits).
-struct WaveMlp {
-    float w1[19], w2[64], b1, b2, w3, b3;
-    __device__ void load(const uint16_t *wbf16, const float *w32, int lane)
+// The scorer's weights in LDS, unit-minor so that lane o of a wave reads
+// unit o's weight for input k from consecutive words (no bank conflicts).
+struct MlpWave {
+    float w1[19][64], w2[64][64], b1[64], b2[64], w3[64], b3;
+    // Thread tid's share of the weights, fetched into registers early and
+    // written to LDS later (put), so that the global reads overlap other work.
+    struct Share {
+        float a[5], c[16], e[3], f;
+    };
+    __device__ static Share fetch(const uint16_t *wbf16, const float *w32, int tid)
     {
+        Share r;
 #pragma unroll
-        for (int k = 0; k < 19; ++k) w1[k] = bf2f(wbf16[kW1 + 19 * lane + k]);
+        for (int u = 0; u < 5; ++u) r.a[u] = tid + 256 * u < 19 * 64 ? bf2f(wbf16[kW1 + tid + 256 * u]) : 0.0f;
 #pragma unroll
-        for (int k = 0; k < 64; ++k) w2[k] = bf2f(wbf16[kW2 + 64 * lane + k]);
-        b1 = w32[kB1 + lane];
-        b2 = w32[kB2 + lane];
-        w3 = bf2f(wbf16[kW3 + lane]);
-        b3 = w32[kB3];
+        for (int u = 0; u < 16; ++u) r.c[u] = bf2f(wbf16[kW2 + tid + 256 * u]);
+        const int t = tid & 63;
+        r.e[0] = w32[kB1 + t];
+        r.e[1] = w32[kB2 + t];
+        r.e[2] = bf2f(wbf16[kW3 + t]);
+        r.f = w32[kB3];
+        return r;
     }
-    __device__ float score(uint16_t fb) const
+    // By a whole 256-thread workgroup; the caller synchronises after.
+    __device__ void put(const Share &r, int tid)
     {
-        float acc = b1;
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            const int t = tid + 256 * u;
+            if (t < 19 * 64) w1[t % 19][t / 19] = r.a[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int t = tid + 256 * u;
+            w2[t & 63][t >> 6] = r.c[u];
+        }
+        if (tid < 64) {
+            b1[tid] = r.e[0];
+            b2[tid] = r.e[1];
+            w3[tid] = r.e[2];
+        }
+        if (tid == 0) b3 = r.f;
+    }
+    // Score of one match by a whole wave: lane o computes hidden unit o, each
+    // layer one multiply-add chain per lane over inputs broadcast with
+    // v_readlane, in the same order as the one-thread forward pass. fb: lane
+    // k < 19 holds feature k (bfloat16 bits).
+    __device__ float score(uint16_t fb, int lane) const
+    {
+        float acc = b1[lane];
 #pragma unroll
         for (int k = 0; k < 19; ++k)
-            acc = __builtin_fmaf(w1[k], bf2f((uint16_t)__builtin_amdgcn_readlane((int)fb, k)), acc);
+            acc = __builtin_fmaf(w1[k][lane], bf2f((uint16_t)__builtin_amdgcn_readlane((int)fb, k)), acc);
         const float a1 = bfround(gelu(acc));
-        acc = b2;
+        acc = b2[lane];
 #pragma unroll
-        for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(w2[k], lane_f(a1, k), acc);
+        for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(w2[k][lane], lane_f(a1, k), acc);
         const float a2 = bfround(gelu(acc));
+        const float w3l = w3[lane];
         float s = b3;
 #pragma unroll
-        for (int o = 0; o < 64; ++o) s = __builtin_fmaf(lane_f(w3, o), lane_f(a2, o), s);
+        for (int o = 0; o < 64; ++o) s = __builtin_fmaf(lane_f(w3l, o), lane_f(a2, o), s);
         return s;
     }
 };
 
-// Feature k of a match (lane k < 19) from its integer accumulators, as k_features.
-__device__ __forceinline__ uint16_t feature_bits(const int32_t *rs, int k, int n)
+// Feature k of a match from its integer accumulator v, as k_features.
+__device__ __forceinline__ uint16_t feature_bits(int32_t v, int k, int n)
 {
     const double n1 = (double)(n - 1), nn = (double)n;
-    return f2bf((float)((double)rs[k] / (k == 0 ? n1 : k == 1 ? n1 * nn : k == 2 ? nn : n1)));
+    return f2bf((float)((double)v / (k == 0 ? n1 : k == 1 ? n1 * nn : k == 2 ? nn : n1)));
 }
 
+constexpr int kCandRows = 4;   // rows evaluated together against each loaded point
+
 // Features and score of every match the reorder needs: the endpoints of the
-// pair's plain pivot pool. Each distinct row is claimed by one workgroup
-// (compare-and-swap on its mark), which evaluates delta_ij for all j != i
-// exactly as the compatibility kernel does (same operation order, correctly
-// rounded square roots) to count the degree and the 16-bin delta histogram;
-// the SC2 row sum and maximum come from the SC2 epilogue. Wave 0 then scores
-// the match. Matches outside the pool get no features and no score.
-__global__ void __launch_bounds__(256) k_cand_rows(Work w, int B, const uint16_t *wbf16, const float *w32)
+// pair's plain pivot pool. The endpoints are cut into chunks of R (at most
+// kCandRows); wave 0 claims each distinct row of its chunk by compare-and-swap
+// on the row's mark, so every row is evaluated once. The workgroup then reads
+// each of the pair's points once and evaluates delta_ij against all claimed
+// rows, exactly as the compatibility kernel does (same operation order,
+// correctly rounded square roots), counting the degree and the 16-bin delta
+// histogram; the SC2 row sum and maximum come from the SC2 epilogue. Each wave
+// then scores the rows of its slot. Matches outside the pool get no features
+// and no score.
+__global__ void __launch_bounds__(256) k_cand_rows(Work w, int B, int R, const uint16_t *wbf16, const float *w32)
 {
-    __shared__ int32_t red[4][17];
-    __shared__ int32_t own;
-    __shared__ int32_t rs_l[20];
+    __shared__ float crd[kCandRows][6];
+    __shared__ int32_t row_l[kCandRows];
+    __shared__ int32_t cnt_l;
+    __shared__ int32_t red[4][kCandRows][9];
+    __shared__ MlpWave mlp;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    WaveMlp mlp;
-    if (wv == 0) mlp.load(wbf16, w32, lane);
+    const MlpWave::Share share = MlpWave::fetch(wbf16, w32, tid);
+    bool staged = false;   // weights written to LDS (before the first scoring)
     const float tau = w.tau, q = tau * 0.25f;
     float edge[16];
 #pragma unroll
     for (int k = 1; k < 16; ++k) edge[k] = (float)k * q;   // bin edges as the compatibility kernel forms them
-    const int per_pair = 2 * w.pool, total = B * per_pair;
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = item / per_pair, e = item - b * per_pair;
+    const int cpp = (2 * w.pool + R - 1) / R, total = B * cpp;
+    for (int c = blockIdx.x; c < total; c += gridDim.x) {
+        const int b = c / cpp, e0 = (c - b * cpp) * R;
         const PairDesc d = pair_desc(w, b);
-        if ((e >> 1) >= d.kpiv) continue;   // same for the whole workgroup
-        const int i = w.pivots_plain[((int64_t)b * w.pool_cap + (e >> 1)) * 3 + (e & 1)];
-        if (i < 0 || i >= d.n) continue;
-        if (tid == 0) own = atomicCAS(&w.mark[(int64_t)b * w.max_n + i], 0, 1) == 0;
-        __syncthreads();
-        const bool mine = own;
-        __syncthreads();
-        if (!mine) continue;
-        const int64_t gi = d.pt_off + i;
-        const float xi0 = w.src[3 * gi], xi1 = w.src[3 * gi + 1], xi2 = w.src[3 * gi + 2];
-        const float yi0 = w.dst[3 * gi], yi1 = w.dst[3 * gi + 1], yi2 = w.dst[3 * gi + 2];
-        uint32_t cw[4] = {0, 0, 0, 0};   // 16 bins, 8 bits each (at most ceil(32767/256) per thread)
-        int deg = 0;
-        constexpr int kU = 8;             // point loads in flight per thread
-        for (int j0 = tid; j0 < d.n; j0 += 256 * kU) {
-            float p[kU][6];
+        if (e0 >= 2 * d.kpiv) continue;   // same for the whole workgroup
+        // The first batch of points is fetched before the rows are claimed.
+        constexpr int kU = 8;   // point loads in flight per thread
+        float p[kU][6];
+        auto fetch_points = [&](int j0) {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int64_t gj = d.pt_off + min(j0 + 256 * u, d.n - 1);
-                p[u][0] = w.src[3 * gj]; p[u][1] = w.src[3 * gj + 1]; p[u][2] = w.src[3 * gj + 2];
-                p[u][3] = w.dst[3 * gj]; p[u][4] = w.dst[3 * gj + 1]; p[u][5] = w.dst[3 * gj + 2];
+                const float3 a = *reinterpret_cast<const float3 *>(w.src + 3 * gj);   // one 12-byte load
+                const float3 c = *reinterpret_cast<const float3 *>(w.dst + 3 * gj);
+                p[u][0] = a.x; p[u][1] = a.y; p[u][2] = a.z;
+                p[u][3] = c.x; p[u][4] = c.y; p[u][5] = c.z;
             }
+        };
+        fetch_points(tid);
+        if (wv == 0) {
+            const int e = e0 + lane;
+            int i = -1;
+            if (lane < R && e < 2 * d.kpiv) {
+                i = w.pivots_plain[((int64_t)b * w.pool_cap + (e >> 1)) * 3 + (e & 1)];
+                if (i < 0 || i >= d.n || atomicCAS(&w.mark[(int64_t)b * w.max_n + i], 0, 1) != 0) i = -1;
+            }
+            const uint64_t m = __ballot(i >= 0);
+            if (i >= 0) {
+                const int pos = __popcll(m & ((1ull << lane) - 1ull));
+                const int64_t gi = d.pt_off + i;
+                row_l[pos] = i;
+                crd[pos][0] = w.src[3 * gi]; crd[pos][1] = w.src[3 * gi + 1]; crd[pos][2] = w.src[3 * gi + 2];
+                crd[pos][3] = w.dst[3 * gi]; crd[pos][4] = w.dst[3 * gi + 1]; crd[pos][5] = w.dst[3 * gi + 2];
+            }
+            if (lane == 0) cnt_l = __popcll(m);
+        }
+        __syncthreads();
+        const int cnt = cnt_l;
+        if (cnt == 0) {
+            __syncthreads();   // cnt_l is the next chunk's
+            continue;
+        }
+        uint32_t cw[kCandRows][4];   // 16 bins, 8 bits each (at most ceil(32767/256) per thread)
+        int deg[kCandRows];
+#pragma unroll
+        for (int r = 0; r < kCandRows; ++r) {
+            deg[r] = 0;
+            cw[r][0] = cw[r][1] = cw[r][2] = cw[r][3] = 0;
+        }
+        for (int j0 = tid; j0 < d.n; j0 += 256 * kU) {
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int j = j0 + 256 * u;
-                const float lx = length32(xi0 - p[u][0], xi1 - p[u][1], xi2 - p[u][2]);
-                const float ly = length32(yi0 - p[u][3], yi1 - p[u][4], yi2 - p[u][5]);
-                const float dl = __builtin_fabsf(lx - ly);
-                const bool in = j < d.n && j != i;
-                deg += in && dl <= tau;
-                int bin = 0;
 #pragma unroll
-                for (int k = 1; k < 16; ++k) bin += dl >= edge[k];
-                const uint32_t inc = in ? 1u << (8 * (bin & 3)) : 0u;
-                cw[0] += (bin >> 2) == 0 ? inc : 0u;
-                cw[1] += (bin >> 2) == 1 ? inc : 0u;
-                cw[2] += (bin >> 2) == 2 ? inc : 0u;
-                cw[3] += (bin >> 2) == 3 ? inc : 0u;
-            }
-        }
+                for (int r = 0; r < kCandRows; ++r) {
+                    if (r >= cnt) break;
+                    const float lx = length32(crd[r][0] - p[u][0], crd[r][1] - p[u][1], crd[r][2] - p[u][2]);
+                    const float ly = length32(crd[r][3] - p[u][3], crd[r][4] - p[u][4], crd[r][5] - p[u][5]);
+                    const float dl = __builtin_fabsf(lx - ly);
+                    const bool in = j < d.n && j != row_l[r];
+                    deg[r] += in && dl <= tau;
+                    int bin = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int t = wave_total((int)((cw[k >> 2] >> (8 * (k & 3))) & 0xFFu));
-            if (lane == 0) red[wv][1 + k] = t;
-        }
-        deg = wave_total(deg);
-        if (lane == 0) red[wv][0] = deg;
-        __syncthreads();
-        int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
-        if (tid < 19) {
-            int v;
-            if (tid == 0 || tid >= 3) {   // degree, histogram bins 0..15
-                const int f = tid == 0 ? 0 : tid - 2;
-                v = red[0][f] + red[1][f] + red[2][f] + red[3][f];
-                rs[tid] = v;
-            } else {
-                v = rs[tid];   // SC2 row sum / maximum
+                    for (int k = 1; k < 16; ++k) bin += dl >= edge[k];
+                    const uint32_t inc = in ? 1u << (8 * (bin & 3)) : 0u;
+                    cw[r][0] += (bin >> 2) == 0 ? inc : 0u;
+                    cw[r][1] += (bin >> 2) == 1 ? inc : 0u;
+                    cw[r][2] += (bin >> 2) == 2 ? inc : 0u;
+                    cw[r][3] += (bin >> 2) == 3 ? inc : 0u;
+                }
             }
-            rs_l[tid] = v;
+            if (j0 + 256 * kU < d.n) fetch_points(j0 + 256 * kU);
         }
+        // Per row: bytes 0,2 and 1,3 of each counter word widen to 16-bit
+        // fields (a workgroup's count of one bin is below 2^15).
+#pragma unroll
+        for (int r = 0; r < kCandRows; ++r) {
+            if (r >= cnt) break;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int te = wave_total((int)(cw[r][m] & 0x00FF00FFu));
+                const int to = wave_total((int)((cw[r][m] >> 8) & 0x00FF00FFu));
+                if (lane == 0) {
+                    red[wv][r][2 * m] = te;
+                    red[wv][r][2 * m + 1] = to;
+                }
+            }
+            const int td = wave_total(deg[r]);
+            if (lane == 0) red[wv][r][8] = td;
+        }
+        if (!staged) mlp.put(share, tid);
+        staged = true;
         __syncthreads();
-        if (wv == 0) {
+#pragma unroll 1
+        for (int r = wv; r < cnt; r += 4) {
+            const int i = row_l[r];
+            int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+            int32_t v = 0;
+            if (lane == 0) {
+                v = red[0][r][8] + red[1][r][8] + red[2][r][8] + red[3][r][8];
+            } else if (lane < 3) {
+                v = rs[lane];   // SC2 row sum / maximum
+            } else if (lane < 19) {
+                const int bin = lane - 3, idx = 2 * (bin >> 2) + (bin & 1), sh = 16 * ((bin >> 1) & 1);
+#pragma unroll
+                for (int g = 0; g < 4; ++g) v += (red[g][r][idx] >> sh) & 0xFFFF;
+            }
             uint16_t fb = 0;
             if (lane < 19) {
-                fb = feature_bits(rs_l, lane, d.n);
+                if (lane == 0 || lane >= 3) rs[lane] = v;
+                fb = feature_bits(v, lane, d.n);
                 w.feat[((int64_t)b * w.max_n + i) * 19 + lane] = fb;
             }
-            const float sc = mlp.score(fb);
+            const float sc = mlp.score(fb, lane);
             if (lane == 0) {
                 w.scores[(int64_t)b * w.max_n + i] = sc;
                 if (!isfinite(sc)) atomicOr(&w.state[b].fallback, 1);
             }
         }
-        __syncthreads();   // red and rs_l are the next item's
+        __syncthreads();   // row_l, crd, red and cnt_l are the next chunk's
     }
 }
 
@@ -628,8 +708,12 @@ hipError_t launch_features(const Work &w, uint16_t *packed, int grid, hipStream_
 
 hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int grid, hipStream_t st)
 {
+    // Rows per chunk: few enough chunks that all run at once (two workgroups
+    // per CU fit), at most kCandRows rows each.
     const int cand = B * 2 * w.pool;
-    hipLaunchKernelGGL(k_cand_rows, dim3(min(cand, grid * 4)), dim3(256), 0, st, w, B, mlp.wbf16, mlp.w32);
+    const int R = max(1, min(kCandRows, (cand + 2 * grid - 1) / (2 * grid)));
+    const int chunks = B * ((2 * w.pool + R - 1) / R);
+    hipLaunchKernelGGL(k_cand_rows, dim3(min(chunks, grid * 2)), dim3(256), 0, st, w, B, R, mlp.wbf16, mlp.w32);
     const int bpp = (max(w.pool, w.k1) + 63) / 64;
     hipLaunchKernelGGL(k_reorder, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), st, w,
                        bpp);
