@@ -140,26 +140,38 @@ static int edge_cmp(const void *a, const void *b)
     return 0;
 }
 
+/* All pairs i<j ordered by edge_cmp, first K1 kept. Weights are counts (never
+ * negative), so every zero-weight pair sorts after every positive one and the
+ * zero-weight pairs among themselves in (i, j) order: only the positive pairs
+ * are sorted, and the zero-weight pairs are appended by a row-major scan. The
+ * result equals a sort of all N(N-1)/2 pairs. */
 int64_t tro_pivots(const int32_t *Gbar, int32_t n, int32_t k1, int32_t *P)
 {
     if (!Gbar || !P || n < 0 || k1 < 0) return -1;
-    int64_t m = (int64_t)n * (n - 1) / 2;
-    edge_t *e = (edge_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(edge_t));
+    int64_t m = (int64_t)n * (n - 1) / 2, pos = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j) {
+            if (Gbar[(int64_t)i * n + j] < 0) return -1;
+            pos += Gbar[(int64_t)i * n + j] > 0;
+        }
+    edge_t *e = (edge_t *)malloc((size_t)(pos > 0 ? pos : 1) * sizeof(edge_t));
     if (!e) return -3;
     int64_t c = 0;
     for (int32_t i = 0; i < n; ++i)
-        for (int32_t j = i + 1; j < n; ++j) {
-            e[c].w = Gbar[(int64_t)i * n + j];
-            e[c].i = i;
-            e[c].j = j;
-            ++c;
-        }
-    qsort(e, (size_t)m, sizeof(edge_t), edge_cmp);
-    int64_t np = m < k1 ? m : k1;
-    for (int64_t p = 0; p < k1; ++p) {
-        if (p < np) { P[3 * p] = e[p].i; P[3 * p + 1] = e[p].j; P[3 * p + 2] = e[p].w; }
-        else { P[3 * p] = -1; P[3 * p + 1] = -1; P[3 * p + 2] = 0; }
-    }
+        for (int32_t j = i + 1; j < n; ++j)
+            if (Gbar[(int64_t)i * n + j] > 0) {
+                e[c].w = Gbar[(int64_t)i * n + j];
+                e[c].i = i;
+                e[c].j = j;
+                ++c;
+            }
+    qsort(e, (size_t)pos, sizeof(edge_t), edge_cmp);
+    int64_t np = m < k1 ? m : k1, p = 0;
+    for (; p < np && p < pos; ++p) { P[3 * p] = e[p].i; P[3 * p + 1] = e[p].j; P[3 * p + 2] = e[p].w; }
+    for (int32_t i = 0; i < n && p < np; ++i)
+        for (int32_t j = i + 1; j < n && p < np; ++j)
+            if (Gbar[(int64_t)i * n + j] == 0) { P[3 * p] = i; P[3 * p + 1] = j; P[3 * p + 2] = 0; ++p; }
+    for (; p < k1; ++p) { P[3 * p] = -1; P[3 * p + 1] = -1; P[3 * p + 2] = 0; }
     free(e);
     return np;
 }

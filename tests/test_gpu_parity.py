@@ -62,6 +62,22 @@ def test_indoor_n5000_full_size(reg):
     assert synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
 
 
+def test_outdoor_n20000_full_size():
+    # the outdoor stress workload at full size: every stage against the whole oracle (about 20 s of CPU)
+    cfg = synth.CONFIGS["outdoor_n20000"]
+    p = synth.make_pair(cfg, synth.pair_seed(4, 0))
+    prm = T.params_from_config(cfg)
+    say("outdoor n=20000")
+    r20 = T.Registrar(max_n=cfg.n, max_batch=1, max_k1=cfg.k1, max_k2=cfg.k2)
+    try:
+        r, mask = run_single(r20, torch, p.src, p.dst, prm)
+        d = check_taps(r20, p.src, p.dst, prm, r, mask, label="outdoor n=20000")
+    finally:
+        r20.close()
+    say(d)
+    assert synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
+
+
 @pytest.mark.parametrize("k2", [1, 3, 8])
 def test_k2_values(reg, k2):
     p = indoor(400, 0.3, 7)

@@ -181,6 +181,11 @@ def test_pivots_match_full_sort_with_heavy_ties():
         assert npv == min(k1, n * (n - 1) // 2)
         assert [tuple(r) for r in P[:npv]] == ref
         assert (P[npv:, :2] == -1).all()
+    for n, k1, dens in [(40, 60, 0.03), (40, 780, 0.1), (20, 7, 0.0)]:   # few positive weights: zero pairs fill in
+        W = np.triu(rng.integers(1, 5, (n, n)) * (rng.random((n, n)) < dens), 1).astype(np.int32)
+        P, npv = oracle.pivots(W, k1)
+        allp = sorted(((-int(W[i, j]), i, j) for i in range(n) for j in range(i + 1, n)))
+        assert [tuple(r) for r in P[:npv]] == [(i, j, -w) for w, i, j in allp[:k1]]
 
 
 # ---------------------------------------------------------------- Eqs. 5-8, Appendix C
