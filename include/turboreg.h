@@ -149,12 +149,15 @@ tr_status tr_train_step(tr_handle *h, const uint16_t *feat_dev, const uint8_t *l
 enum {
     TR_TAP_C = 0,         /* N x N uint8 compatibility matrix                          */
     TR_TAP_G = 1,         /* N x N uint16 O2Graph weights (i < j; the tap zeroes j <= i) */
-    TR_TAP_PIVOTS = 2,    /* K x 3 int32 (i, j, w), K = k1 (or the plain pool in learned mode) */
+    TR_TAP_PIVOTS = 2,    /* k1 x 3 int32 (i, j, w): the pivots the cliques used (learned
+                             pivots in learned mode), (-1, -1, 0) past the last     */
     TR_TAP_CLIQUES = 3,   /* H x 3 int32 (i, j, z), H = k1*k2, slot-major, z = -1 empty  */
     TR_TAP_POSES = 4,     /* H x 12 float32 (R row-major, t)                           */
     TR_TAP_IN = 5,        /* H int32 inlier numbers, -1 for an invalid hypothesis      */
-    TR_TAP_FEATURES = 6,  /* N x 19 uint16 bfloat16 features (learned mode)            */
-    TR_TAP_SCORES = 7,    /* N float32 learned scores (learned mode)                   */
+    TR_TAP_FEATURES = 6,  /* N x 19 uint16 bfloat16 features (learned mode; only rows that
+                             are endpoints of the plain pool's pivots are written, the
+                             others keep older values)                                 */
+    TR_TAP_SCORES = 7,    /* N float32 learned scores (learned mode; same rows as above)  */
     TR_TAP_PLAIN_PIVOTS = 8 /* pool x 3 int32 plain pivots before the learned reorder  */
 };
 

@@ -1,6 +1,6 @@
 // Graph construction on gfx950: work planning, the pairwise-length
 // compatibility matrix (Eq. 1) and the SC2 weights of the O2Graph
-// (Eq. 2 restricted to i < j, Definition 2) on int8 MFMA.
+// (Eq. 2 restricted to i < j, Definition 2) on FP4 MFMA with exact float32 accumulation.
 #include "common.h"
 
 namespace tr {
