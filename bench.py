@@ -98,6 +98,7 @@ def main():
                     choices=["indoor_n5000", "indoor_n1000", "batch256", "outdoor16"])
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--learned", action="store_true", help="add the learned-vs-plain comparison (needs weights)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -141,6 +142,15 @@ def main():
                         mask=torch.empty(int(offs[-1]), dtype=torch.uint8, device="cuda")))
     G = len(dev)
     side = torch.cuda.Stream()   # default priority; batches replay a captured hipGraph on it
+
+    # launch configuration: the library's autotuner on the first input group (untimed)
+    tuning = T.tr_tuning_get(reg.h, max_n, B)
+    tuned_ms = None
+    if not args.no_autotune:
+        d = dev[0]
+        tuning, tuned_ms = T.tr_autotune(reg.h, d["src"], d["dst"], None if B == 1 else d["offs"], B,
+                                         d["n"][0] if B == 1 else max_n, plain, d["out"], d["mask"])
+        torch.cuda.synchronize()
 
     def step(k, prm):
         d = dev[k % G]
@@ -216,6 +226,9 @@ def main():
         "gpu_event_ms_per_step": gpu_ms / args.steps,
         "stages_us": {k: round(v * 1000.0, 2) for k, v in stages.items()},
         "dominant_stage": max(stages, key=stages.get),
+        "launch_config": {"autotuned": not args.no_autotune, "sc2_super": tuning.sc2_super,
+                          "compat_per_cu": tuning.compat_per_cu, "hyp_ppw": tuning.hyp_ppw,
+                          "hyp_per_cu": tuning.hyp_per_cu, "autotune_ms_per_call": tuned_ms},
         "roofline": roof,
         "compat_roofline": {"bound": "alu", "achieved": compat_tops, "peak": PEAK_VALU_TOPS,
                             "unit": "TOP/s (VALU lane slots)", "frac": compat_tops / PEAK_VALU_TOPS,

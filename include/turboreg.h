@@ -85,7 +85,7 @@ typedef struct tr_handle tr_handle;
 /* Create a handle on `device` whose workspace holds up to `max_batch` pairs of
  * up to `max_n` matches, K1 <= max_k1 and K2 <= max_k2. Learned mode needs
  * pool_factor*K1 <= min(8*max_k1, TR_MAX_POOL). Allocates device memory
- * (about 3 * max_batch * round_up(max_n,128)^2 bytes); max_n <= 32767. *out is NULL on error. */
+ * (about 2.5 * max_batch * round_up(max_n,256)^2 bytes); max_n <= 32767. *out is NULL on error. */
 tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t max_k1,
                     int32_t max_k2, int32_t device);
 tr_status tr_destroy(tr_handle *h);
@@ -106,6 +106,41 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst,
                             const int32_t *offsets_dev, int32_t B, int32_t max_n,
                             const tr_params *p, tr_result *out_dev, uint8_t *masks_dev,
                             void *stream);
+
+/* ---- launch configuration and autotuner ----
+ * Calls are grouped by shape: the number of 256-row tiles of their largest
+ * pair, round_up(max_n, 256) / 256, and the batch size B (1 for tr_register).
+ * Each group has a launch configuration; a group never tuned or set uses the
+ * defaults (5, 4, 4 for one pair or 16 for a batch, 4). No configuration
+ * changes any result: C, weights, pivots, cliques, poses, inlier numbers and
+ * the selection are the same under every valid configuration. */
+typedef struct {
+    int32_t sc2_super;      /* SC2 tile walk: side of the super-tiles (in 256 x 256
+                               output tiles) whose tiles run close together, 1..16  */
+    int32_t compat_per_cu;  /* compatibility work items launched per CU, 1..16     */
+    int32_t hyp_ppw;        /* pivots per hypothesis work item: 4, 8, 12 or 16     */
+    int32_t hyp_per_cu;     /* hypothesis workgroups launched per CU, 1..16        */
+} tr_tuning;
+
+/* Configuration of the group of (max_n, B). TR_ERR_INVALID_ARG for max_n < 3, B < 1. */
+tr_status tr_tuning_get(tr_handle *h, int32_t max_n, int32_t B, tr_tuning *out);
+/* Set the configuration of the group of (max_n, B); TR_ERR_INVALID_ARG if a
+ * field is outside its range. Later calls of that group use it (batches on a
+ * stream capture a new hipGraph for it). */
+tr_status tr_tuning_set(tr_handle *h, int32_t max_n, int32_t B, const tr_tuning *t);
+/* Autotuner: runs the registration of the given inputs (one pair of N = max_n
+ * if offsets_dev is NULL and B == 1, else the batch as tr_register_batch) under
+ * candidate configurations, one field at a time starting from the group's
+ * current one (hyp_ppw, hyp_per_cu, sc2_super, compat_per_cu), each candidate
+ * timed by HIP events on `stream` over five runs after one warm-up, keeps a
+ * candidate only if it is at least 1% faster, stores the result for the group
+ * and writes it to *best (nullable) with its time per registration call in
+ * *best_ms (nullable). Runs eagerly and synchronises the stream; out_dev and
+ * masks_dev receive the results of the last run. Same argument errors as the
+ * registration calls. */
+tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const int32_t *offsets_dev,
+                      int32_t B, int32_t max_n, const tr_params *p, tr_result *out_dev,
+                      uint8_t *masks_dev, void *stream, tr_tuning *best, float *best_ms);
 
 /* ---- learned pivot scorer (MLP 19 -> 64 -> 64 -> 1, GELU, bfloat16) ---- */
 
@@ -175,10 +210,9 @@ enum { TR_STAGE_PLAN = 0, TR_STAGE_COMPAT, TR_STAGE_SC2, TR_STAGE_PIVOTS, TR_STA
  * other calls recorded them) since the previous read (HIP events recorded on each call's stream, kept in
  * a ring so profiled calls never wait on the host). Synchronises those events
  * and resets the averages. TR_ERR_INVALID_ARG if no profiled call was made.
- * count <= TR_NUM_STAGES. The rigid fits run inside the clique kernel and the
- * selection inside the scoring kernel, so TR_STAGE_CLIQUES includes the
- * Kabsch fits, TR_STAGE_SCORE includes the selection, and the KABSCH and
- * SELECT entries are zero. */
+ * count <= TR_NUM_STAGES. Cliques, rigid fits, scoring and selection run in
+ * one kernel, timed as TR_STAGE_CLIQUES; the KABSCH, SCORE and SELECT entries
+ * time back-to-back events only. */
 tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count);
 
 const char *tr_status_string(int32_t status);

@@ -65,6 +65,7 @@ struct Work {
     int32_t k1, k2, pool;     // pool = plain pivots selected (k1, or pool_factor*k1 in learned mode)
     int32_t H;                // k1 * k2 hypotheses per pair
     int32_t graph;
+    int32_t sc2_super;        // SC2 tile walk: super-tile side in output tiles (launch configuration)
     float tau, theta;
     uint8_t *C;               // C arena
     uint16_t *G;              // G arena
@@ -225,7 +226,7 @@ hipError_t launch_compat(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
 hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
-hipError_t launch_hyp(const Work &w, int B, int num_cus, hipStream_t s);
+hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s);
 hipError_t setup_hyp_kernels();
 
 // Once per process and device, before any launch (and so outside stream capture):

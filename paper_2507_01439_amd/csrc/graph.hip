@@ -27,18 +27,17 @@ __device__ __forceinline__ void tri_decode(int t, int nb, int &bi, int &bj)
 }
 
 // SC2 tile order: the upper triangle of nb x nb tiles is walked in super-tiles
-// of kSuper x kSuper (super-rows I <= J, row-major), tiles row-major inside.
+// of sup x sup (super-rows I <= J, row-major), tiles row-major inside.
 // Consecutive items then share few row blocks of C, so the tiles one XCD runs
-// at the same time reuse each other's operand rows in its L2.
-constexpr int kSuper = 5;
-
-__device__ __forceinline__ void super_decode(int t, int nb, int &bi, int &bj)
+// at the same time reuse each other's operand rows in its L2. sup >= 1 is a
+// launch parameter (the autotuner's); the order does not change any result.
+__device__ __forceinline__ void super_decode(int t, int nb, int sup, int &bi, int &bj)
 {
-    const int ns = (nb + kSuper - 1) / kSuper;
+    const int ns = (nb + sup - 1) / sup;
     for (int I = 0; I < ns; ++I) {
-        const int r0 = I * kSuper, r1 = min(nb, r0 + kSuper);
+        const int r0 = I * sup, r1 = min(nb, r0 + sup);
         for (int J = I; J < ns; ++J) {
-            const int c0 = J * kSuper, c1 = min(nb, c0 + kSuper);
+            const int c0 = J * sup, c1 = min(nb, c0 + sup);
             int cnt;
             if (I == J) { const int s = r1 - r0; cnt = s * (s + 1) / 2; }
             else cnt = (r1 - r0) * (c1 - c0);
@@ -446,7 +445,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         const int b = stage_pair(w, kSc2, item, local);
         const PairDesc d = pair_desc(w, b);
         int bi, bj;
-        super_decode(local, d.npad / kSc2Tile, bi, bj);
+        super_decode(local, d.npad / kSc2Tile, w.sc2_super, bi, bj);
         const uint8_t *Cb = w.C + d.c_off / 2;
         const int64_t rs = d.npad / 2;       // packed row bytes
         const int nk = (int)(rs / kBK);

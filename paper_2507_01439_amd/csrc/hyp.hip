@@ -543,11 +543,13 @@ hipError_t setup_hyp_kernels()
     return hipSuccess;
 }
 
-hipError_t launch_hyp(const Work &w, int B, int num_cus, hipStream_t s)
+// ppw: pivots per work item, a multiple of 4 up to 16 (the LDS pose slots);
+// grid: workgroups to launch (capped at the number of items).
+hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s)
 {
-    const int ppw = B == 1 ? 4 : 16;   // batches: more pivots per workgroup, fewer passes over each pair's matches
+    if (ppw < 4 || ppw > 16 || ppw % 4) return hipErrorInvalidValue;
     const int total = B * ((w.k1 + ppw - 1) / ppw);
-    const int grid = min(total, num_cus * 4);
+    grid = max(1, min(total, grid));
     if (w.k2 <= 2) hipLaunchKernelGGL(k_hyp<2>, dim3(grid), dim3(256), 0, s, w, B, ppw);
     else hipLaunchKernelGGL(k_hyp<TR_MAX_K2>, dim3(grid), dim3(256), 0, s, w, B, ppw);
     return hipGetLastError();

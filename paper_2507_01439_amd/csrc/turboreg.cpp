@@ -24,6 +24,7 @@ struct GraphKey {
     void *stream;
     int32_t B, max_n;
     tr_params p;
+    tr_tuning cfg;
     bool operator<(const GraphKey &o) const
     {
         return std::memcmp(this, &o, sizeof(GraphKey)) < 0;
@@ -70,6 +71,8 @@ struct tr_handle {
     int64_t stage_calls[TR_NUM_STAGES] = {};
     // captured batches
     std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // launch configurations by (256-row tiles of the largest pair, batch size)
+    std::map<std::pair<int32_t, int32_t>, tr_tuning> tuning;
     std::vector<void *> allocs;
 };
 
@@ -101,6 +104,29 @@ void release(tr_handle *h)
     h->allocs.clear();
 }
 
+std::pair<int32_t, int32_t> tuning_key(int32_t max_n, int32_t B)
+{
+    return {(max_n + kSc2Tile - 1) / kSc2Tile, B};
+}
+
+tr_tuning tuning_for(const tr_handle *h, int32_t max_n, int32_t B)
+{
+    auto it = h->tuning.find(tuning_key(max_n, B));
+    if (it != h->tuning.end()) return it->second;
+    tr_tuning t;
+    t.sc2_super = 5;
+    t.compat_per_cu = 4;
+    t.hyp_ppw = B == 1 ? 4 : 16;   // batches: more pivots per workgroup, fewer passes over each pair's matches
+    t.hyp_per_cu = 4;
+    return t;
+}
+
+bool tuning_valid(const tr_tuning &t)
+{
+    return t.sc2_super >= 1 && t.sc2_super <= 16 && t.compat_per_cu >= 1 && t.compat_per_cu <= 16 &&
+           t.hyp_ppw >= 4 && t.hyp_ppw <= 16 && t.hyp_ppw % 4 == 0 && t.hyp_per_cu >= 1 && t.hyp_per_cu <= 16;
+}
+
 int grid_cap(tr_handle *h, int64_t items, int per_cu)
 {
     int64_t cap = (int64_t)h->num_cus * per_cu;
@@ -125,6 +151,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.pool = learned ? p.k1 * p.pool_factor : p.k1;
     w.H = p.k1 * p.k2;
     w.graph = p.graph;
+    w.sc2_super = 5;
     w.tau = p.tau;
     w.theta = p.inlier_thresh;
     w.C = h->C;
@@ -175,9 +202,12 @@ tr_status check_params(tr_handle *h, const tr_params *p)
 
 // The launch sequence for B pairs (offsets on the device) or one pair (n_single).
 // features_only stops after the learned features.
-tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n_single, int32_t B,
-                  int32_t max_n, hipEvent_t *ev, int ev_mode, bool features_only, hipStream_t s)
+tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_t n_single, int32_t B,
+                  int32_t max_n, hipEvent_t *ev, int ev_mode, bool features_only, hipStream_t s,
+                  const tr_tuning &cfg)
 {
+    Work w = w_in;
+    w.sc2_super = cfg.sc2_super;
     const bool profile = ev != nullptr;
     const int64_t npad = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
     const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
@@ -194,7 +224,7 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     if (w.learned && w.feat_all)
         chk(launch_prep_learned(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
     mark(TR_STAGE_COMPAT);
-    chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, 4), s));   // one round of resident workgroups
+    chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, cfg.compat_per_cu), s));
     mark(TR_STAGE_SC2);
     {
         // one workgroup per CU; the kernel splits its items into 8 equal ranges, one per XCD
@@ -214,7 +244,7 @@ tr_status enqueue(tr_handle *h, const Work &w, const int32_t *offsets, int32_t n
     }
     mark(TR_STAGE_CLIQUES);
     // cliques, their poses, their inlier counts and (last workgroup per pair) the selection
-    chk(launch_hyp(w, B, h->num_cus, s));
+    chk(launch_hyp(w, B, cfg.hyp_ppw, h->num_cus * cfg.hyp_per_cu, s));
     mark(TR_STAGE_KABSCH);
     mark(TR_STAGE_SCORE);
     mark(TR_STAGE_SELECT);
@@ -392,7 +422,7 @@ tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t *ev = nullptr;
     if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
-    st = enqueue(h, w, nullptr, n, 1, n, ev, pmode, false, s);
+    st = enqueue(h, w, nullptr, n, 1, n, ev, pmode, false, s, tuning_for(h, n, 1));
     if (st == TR_OK) remember(h, w, 1, s);
     return st;
 }
@@ -409,11 +439,12 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     const int pmode = profile_mode(p->flags);
     Work w = make_work(h, src, dst, *p, out_dev, masks_dev, learned, B, max_n);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const tr_tuning cfg = tuning_for(h, max_n, B);
     if (pmode || s == nullptr) {
         // events (and the legacy default stream) stay out of captured graphs: run eagerly
         hipEvent_t *ev = nullptr;
         if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, pmode, false, s);
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, pmode, false, s, cfg);
         if (st == TR_OK) remember(h, w, B, s);
         return st;
     }
@@ -428,12 +459,13 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     key.B = B;
     key.max_n = max_n;
     key.p = *p;
+    key.cfg = cfg;
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_ERR_HIP;
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, false, s);
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, false, s, cfg);
         hipError_t ec = hipStreamEndCapture(s, &g);
         if (st != TR_OK || ec != hipSuccess) {
             if (g) hipGraphDestroy(g);
@@ -447,6 +479,90 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     }
     if (hipGraphLaunch(it->second.second, s) != hipSuccess) return TR_ERR_HIP;
     remember(h, w, B, s);
+    return TR_OK;
+}
+
+tr_status tr_tuning_get(tr_handle *h, int32_t max_n, int32_t B, tr_tuning *out)
+{
+    if (!h || !out || max_n < 3 || B < 1) return TR_ERR_INVALID_ARG;
+    *out = tuning_for(h, max_n, B);
+    return TR_OK;
+}
+
+tr_status tr_tuning_set(tr_handle *h, int32_t max_n, int32_t B, const tr_tuning *t)
+{
+    if (!h || !t || max_n < 3 || B < 1 || !tuning_valid(*t)) return TR_ERR_INVALID_ARG;
+    h->tuning[tuning_key(max_n, B)] = *t;
+    return TR_OK;
+}
+
+tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const int32_t *offsets_dev, int32_t B,
+                      int32_t max_n, const tr_params *p, tr_result *out_dev, uint8_t *masks_dev, void *stream,
+                      tr_tuning *best, float *best_ms)
+{
+    if (!h || !src || !dst || !out_dev || B < 1 || max_n < 3) return TR_ERR_INVALID_ARG;
+    if (!offsets_dev && B != 1) return TR_ERR_INVALID_ARG;
+    if (B > h->max_batch || max_n > h->max_n) return TR_ERR_WORKSPACE;
+    tr_status st = check_params(h, p);
+    if (st != TR_OK) return st;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    const bool learned = p->pivot_mode == TR_PIVOTS_LEARNED;
+    Work w = make_work(h, src, dst, *p, out_dev, masks_dev, learned, B, max_n);
+    const int32_t n_single = offsets_dev ? 0 : max_n;
+    if (!offsets_dev) w.n1 = max_n;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return TR_ERR_HIP;
+    }
+    constexpr int kRuns = 5;
+    // average milliseconds of one call under configuration c (one untimed warm-up)
+    auto time_cfg = [&](const tr_tuning &c, float &ms) -> tr_status {
+        for (int r = 0; r <= kRuns; ++r) {
+            if (r == 1 && hipEventRecord(e0, s) != hipSuccess) return TR_ERR_HIP;
+            tr_status q = enqueue(h, w, offsets_dev, n_single, B, max_n, nullptr, 0, false, s, c);
+            if (q != TR_OK) return q;
+        }
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return TR_ERR_HIP;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TR_ERR_HIP;
+        ms /= kRuns;
+        return TR_OK;
+    };
+    tr_tuning cur = tuning_for(h, max_n, B);
+    float cur_ms = 0.0f;
+    st = time_cfg(cur, cur_ms);
+    static const int kPpw[] = {4, 8, 16}, kPerCu[] = {2, 4, 8}, kSuper[] = {3, 4, 5, 6, 8}, kCompat[] = {2, 4, 8};
+    struct Field {
+        int32_t tr_tuning::*f;
+        const int *v;
+        int n;
+    };
+    const Field fields[] = {{&tr_tuning::hyp_ppw, kPpw, 3},
+                            {&tr_tuning::hyp_per_cu, kPerCu, 3},
+                            {&tr_tuning::sc2_super, kSuper, 5},
+                            {&tr_tuning::compat_per_cu, kCompat, 3}};
+    for (const Field &fd : fields) {
+        const int32_t start = cur.*fd.f;
+        for (int k = 0; k < fd.n && st == TR_OK; ++k) {
+            if (fd.v[k] == start) continue;
+            tr_tuning c = cur;
+            c.*fd.f = fd.v[k];
+            float ms = 0.0f;
+            st = time_cfg(c, ms);
+            if (st == TR_OK && ms < 0.99f * cur_ms) {
+                cur = c;
+                cur_ms = ms;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != TR_OK) return st;
+    h->tuning[tuning_key(max_n, B)] = cur;
+    remember(h, w, B, s);
+    if (best) *best = cur;
+    if (best_ms) *best_ms = cur_ms;
     return TR_OK;
 }
 
@@ -464,7 +580,7 @@ tr_status tr_features_batch(tr_handle *h, const float *src, const float *dst, co
     Work w = make_work(h, src, dst, q, h->scratch_out, nullptr, true, B, max_n);
     w.feat_all = 1;   // every match's features (training data)
     hipStream_t s = static_cast<hipStream_t>(stream);
-    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, true, s);
+    tr_status st = enqueue(h, w, offsets_dev, 0, B, max_n, nullptr, 0, true, s, tuning_for(h, max_n, B));
     if (st != TR_OK) return st;
     if (launch_features(w, feat_dev, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s) !=
         hipSuccess)

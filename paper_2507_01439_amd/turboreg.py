@@ -29,7 +29,8 @@ TR_NUM_STAGES = len(STAGES)
 
 EXPORTS = ("tr_create", "tr_destroy", "tr_register", "tr_register_batch", "tr_scorer_load",
            "tr_scorer_save", "tr_scorer_set", "tr_scorer_get", "tr_features_batch", "tr_mlp_forward",
-           "tr_mlp_grads", "tr_train_step", "tr_debug_copy", "tr_stage_times", "tr_status_string")
+           "tr_mlp_grads", "tr_train_step", "tr_debug_copy", "tr_stage_times", "tr_status_string",
+           "tr_tuning_get", "tr_tuning_set", "tr_autotune")
 
 
 class tr_params(ct.Structure):
@@ -45,7 +46,12 @@ class tr_result(ct.Structure):
                 ("reserved", ct.c_int32)]
 
 
-assert ct.sizeof(tr_result) == 80 and ct.sizeof(tr_params) == 32
+class tr_tuning(ct.Structure):
+    _fields_ = [("sc2_super", ct.c_int32), ("compat_per_cu", ct.c_int32), ("hyp_ppw", ct.c_int32),
+                ("hyp_per_cu", ct.c_int32)]
+
+
+assert ct.sizeof(tr_result) == 80 and ct.sizeof(tr_params) == 32 and ct.sizeof(tr_tuning) == 16
 
 _lib = None
 
@@ -72,6 +78,10 @@ def lib():
         L.tr_train_step.argtypes = [vp, vp, vp, I64, ct.c_float, vp, vp]
         L.tr_debug_copy.argtypes = [vp, I32, I32, vp, ct.c_size_t, ct.POINTER(ct.c_size_t)]
         L.tr_stage_times.argtypes = [vp, ct.POINTER(ct.c_float), I32]
+        L.tr_tuning_get.argtypes = [vp, I32, I32, ct.POINTER(tr_tuning)]
+        L.tr_tuning_set.argtypes = [vp, I32, I32, ct.POINTER(tr_tuning)]
+        L.tr_autotune.argtypes = [vp, vp, vp, vp, I32, I32, ct.POINTER(tr_params), vp, vp, vp,
+                                  ct.POINTER(tr_tuning), ct.POINTER(ct.c_float)]
         L.tr_status_string.argtypes = [I32]
         L.tr_status_string.restype = ct.c_char_p
         for name in EXPORTS:
@@ -141,6 +151,24 @@ def tr_register(h, src, dst, n, params, out, mask=None):
 def tr_register_batch(h, src, dst, offsets, B, max_n, params, out, masks=None):
     _ck(lib().tr_register_batch(h, _ptr(src), _ptr(dst), _ptr(offsets), int(B), int(max_n), ct.byref(params),
                                 _ptr(out), _ptr(masks), _stream()), "tr_register_batch")
+
+
+def tr_tuning_get(h, max_n, B=1) -> tr_tuning:
+    t = tr_tuning()
+    _ck(lib().tr_tuning_get(h, int(max_n), int(B), ct.byref(t)), "tr_tuning_get")
+    return t
+
+
+def tr_tuning_set(h, max_n, B, t: tr_tuning):
+    _ck(lib().tr_tuning_set(h, int(max_n), int(B), ct.byref(t)), "tr_tuning_set")
+
+
+def tr_autotune(h, src, dst, offsets, B, max_n, params, out, masks=None):
+    """Returns (best tr_tuning, milliseconds per call under it); offsets None = one pair of N = max_n."""
+    t, ms = tr_tuning(), ct.c_float()
+    _ck(lib().tr_autotune(h, _ptr(src), _ptr(dst), _ptr(offsets), int(B), int(max_n), ct.byref(params), _ptr(out),
+                          _ptr(masks), _stream(), ct.byref(t), ct.byref(ms)), "tr_autotune")
+    return t, float(ms.value)
 
 
 def tr_features_batch(h, src, dst, offsets, B, max_n, params, feat):
