@@ -368,9 +368,11 @@ constexpr int kBK = 64;                        // bytes of a packed row per pipe
 constexpr int kStages = 4;                     // LDS ring depth (three stages in flight)
 constexpr int kMatBytes = kSc2Tile * kBK;      // one operand's stage: 256 rows x 64 bytes
 constexpr int kStageBytes = 2 * kMatBytes;
-constexpr int kRingBytes = kStages * kStageBytes;   // 128 KiB; also holds the finished tile as uint16
+constexpr int kRingBytes = kStages * kStageBytes;   // 128 KiB
+constexpr int kTileBytes = kSc2Tile * kSc2Tile * 2;  // the finished tile as uint16 (128 KiB), over the ring
 constexpr int kHistLdsBins = 8192;             // weights below this are histogrammed in LDS first
-constexpr int kSc2Lds = kRingBytes + kHistLdsBins * 4;   // 160 KiB
+constexpr int kSc2Lds = kRingBytes + kHistLdsBins * 4;   // 160 KiB: ring (then tile), histogram
+static_assert(kTileBytes <= kRingBytes, "the finished tile must fit the ring");
 constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then the low 16 bits of 2^23 + v
 
 // Wait until at most N vector-memory loads of this wave are outstanding, then
@@ -414,7 +416,7 @@ __device__ __forceinline__ int half_sum(int v)
 // Four waves in a 2 x 2 layout each own a 128 x 128 sub-tile as 4 x 4 blocks
 // of 32 x 32 (accumulators in AGPRs). Stages of 64 bytes (128 k) arrive by
 // direct global->LDS 16-byte loads into a four-deep ring, three stages in
-// flight; a row's four 16-byte chunks are stored XOR-swizzled by (row/4) mod 4
+// flight (a fifth stage in flight measured slower); a row's four 16-byte chunks are stored XOR-swizzled by (row/4) mod 4
 // for the fragment reads (ds_read_b128). Work items are split into 8
 // contiguous ranges, one per XCD, so tiles that share rows of C share an L2.
 //
@@ -428,7 +430,7 @@ template <bool LEARNED>
 __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    int32_t *hist = reinterpret_cast<int32_t *>(smem + kRingBytes);
+    int32_t *hist = reinterpret_cast<int32_t *>(smem + kRingBytes);   // zero outside the epilogue
     uint16_t *T = reinterpret_cast<uint16_t *>(smem);
     const int total = stage_total(w, kSc2);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
@@ -549,6 +551,9 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
             for (int q = 0; q < 8; ++q)
                 tv[q] = *reinterpret_cast<const uint4 *>(&T[((kb * 8 + q) * 8 + (tid >> 5)) * kSc2Tile + cc * 8]);
             int rmax[8], rsum[8];
+            uint32_t ow[8][4], nzq[8];
+            // masking, stores and row maxima of the eight rows first (straight-line code), the
+            // histogram of their nonzero weights after
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const int lr = (kb * 8 + q) * 8 + (tid >> 5);
@@ -558,36 +563,57 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 const int e_lo = min(8, max(0, i + 1 - j0)), e_hi = min(8, max(0, d.n - j0));
                 const uint32_t vm = interior ? 0xFFu : (((1u << e_hi) - 1u) & ~((1u << e_lo) - 1u));
                 const uint32_t cb = cur[q] >> 1;   // C of column e at bit 4e
-                uint32_t ow[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     const uint32_t lo = ((cb >> (8 * k)) & 1u) & (vm >> (2 * k));
                     const uint32_t hi = ((cb >> (8 * k + 4)) & 1u) & (vm >> (2 * k + 1));
-                    ow[k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
+                    ow[q][k] = tw[k] & ((lo * 0xFFFFu) | (hi * 0xFFFF0000u));
                 }
                 const u16x2 m2 = __builtin_elementwise_max(
-                    __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[0]), __builtin_bit_cast(u16x2, ow[1])),
-                    __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[2]), __builtin_bit_cast(u16x2, ow[3])));
+                    __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[q][0]), __builtin_bit_cast(u16x2, ow[q][1])),
+                    __builtin_elementwise_max(__builtin_bit_cast(u16x2, ow[q][2]), __builtin_bit_cast(u16x2, ow[q][3])));
                 rmax[q] = max((int)m2.x, (int)m2.y);
                 rsum[q] = 0;
                 if (LEARNED) {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) rsum[q] += (int)((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+                    for (int e = 0; e < 8; ++e) rsum[q] += (int)((ow[q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
                     // the masked tile, for the column pass
-                    *reinterpret_cast<uint4 *>(&T[lr * kSc2Tile + cc * 8]) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+                    *reinterpret_cast<uint4 *>(&T[lr * kSc2Tile + cc * 8]) =
+                        make_uint4(ow[q][0], ow[q][1], ow[q][2], ow[q][3]);
                 }
                 // every chunk is stored whole: entries with j <= i or j >= n are zero and no reader looks at them
-                *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
-                // weight histogram: one LDS atomic per nonzero weight, round by round (a lane's next
-                // nonzero each round), as many rounds as the lane with the most nonzero weights needs
+                *reinterpret_cast<uint4 *>(Gb + (int64_t)i * d.npad + j0) =
+                    make_uint4(ow[q][0], ow[q][1], ow[q][2], ow[q][3]);
                 uint32_t nz = 0;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) nz |= (uint32_t)(((ow[e >> 1] >> (16 * (e & 1))) & 0xFFFFu) != 0) << e;
+                for (int e = 0; e < 8; ++e) nz |= (uint32_t)(((ow[q][e >> 1] >> (16 * (e & 1))) & 0xFFFFu) != 0) << e;
+                nzq[q] = nz;
+            }
+            // weight histogram: one LDS atomic per nonzero weight, round by round (a lane's next
+            // nonzero each round) over four rows at a time, as many rounds as the lane with the
+            // most nonzero weights in them needs. Entry e of the 32: row e / 8, 16 bits at
+            // 16 (e mod 4) of that row's low or high 64-bit half, selected arithmetically (a
+            // lane-varying switch would become branches).
+#pragma unroll
+            for (int g4 = 0; g4 < 2; ++g4) {
+                uint32_t nz = 0;
+                uint64_t h64[8];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = g4 * 4 + u;
+                    nz |= nzq[q] << (8 * u);
+                    h64[2 * u] = (uint64_t)ow[q][0] | ((uint64_t)ow[q][1] << 32);
+                    h64[2 * u + 1] = (uint64_t)ow[q][2] | ((uint64_t)ow[q][3] << 32);
+                }
                 auto next_weight = [&]() -> int {
                     const int e = __builtin_ctz(nz);
                     nz &= nz - 1;
-                    const uint32_t word = (e >> 1) == 0 ? ow[0] : (e >> 1) == 1 ? ow[1] : (e >> 1) == 2 ? ow[2] : ow[3];
-                    return (int)((word >> (16 * (e & 1))) & 0xFFFFu);
+                    const int hsel = e >> 2;   // half index 0..7
+                    const uint64_t a0 = (hsel & 1) ? h64[1] : h64[0], a1 = (hsel & 1) ? h64[3] : h64[2];
+                    const uint64_t a2 = (hsel & 1) ? h64[5] : h64[4], a3 = (hsel & 1) ? h64[7] : h64[6];
+                    const uint64_t b0 = (hsel & 2) ? a1 : a0, b1 = (hsel & 2) ? a3 : a2;
+                    const uint64_t half = (hsel & 4) ? b1 : b0;
+                    return (int)((half >> (16 * (e & 3))) & 0xFFFFu);
                 };
                 if (small_n) {   // every weight is below n <= kHistLdsBins
                     while (__any(nz))
