@@ -486,26 +486,39 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
             else SC2_WAIT_BARRIER(0);
             if (kt + kStages - 1 < nk) issue(kt + kStages - 1);
             const uint8_t *As = smem + (kt % kStages) * kStageBytes, *Bs = As + kMatBytes;
+            // fragment reads run ahead of the MFMAs that use them: the eight of the first half and
+            // the four A fragments of the second are issued before the first MFMA, the four B
+            // fragments of the second half after the first row of four MFMAs (at most twelve LDS
+            // reads outstanding, below the counter's limit); the scheduling barriers keep this order
+            v4i fa[2][4], fb[2][4];
+            auto mfma_row = [&](int ks, int x) {
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int fo = ks ? foff1 : foff0;
-                v4i fa[4], fb[4];
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    fa[x] = *reinterpret_cast<const v4i *>(As + (wm * 128 + x * 32) * kBK + fo);
-                    fb[x] = *reinterpret_cast<const v4i *>(Bs + (wn * 128 + x * 32) * kBK + fo);
+                for (int y = 0; y < 4; ++y) {
+                    // 32 FP4 values of k per lane: 16 bytes, the upper half of the operand is unused
+                    const v8i a8 = {fa[ks][x][0], fa[ks][x][1], fa[ks][x][2], fa[ks][x][3], 0, 0, 0, 0};
+                    const v8i b8 = {fb[ks][y][0], fb[ks][y][1], fb[ks][y][2], fb[ks][y][3], 0, 0, 0, 0};
+                    acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[x][y], 4, 4, 0, 127, 0,
+                                                                                 127);
                 }
+            };
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) {
-                        // 32 FP4 values of k per lane: 16 bytes, the upper half of the operand is unused
-                        const v8i a8 = {fa[x][0], fa[x][1], fa[x][2], fa[x][3], 0, 0, 0, 0};
-                        const v8i b8 = {fb[y][0], fb[y][1], fb[y][2], fb[y][3], 0, 0, 0, 0};
-                        acc[x][y] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, acc[x][y], 4, 4, 0, 127,
-                                                                                     0, 127);
-                    }
+            for (int x = 0; x < 4; ++x) {
+                fa[0][x] = *reinterpret_cast<const v4i *>(As + (wm * 128 + x * 32) * kBK + foff0);
+                fb[0][x] = *reinterpret_cast<const v4i *>(Bs + (wn * 128 + x * 32) * kBK + foff0);
             }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) fa[1][x] = *reinterpret_cast<const v4i *>(As + (wm * 128 + x * 32) * kBK + foff1);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_row(0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int y = 0; y < 4; ++y) fb[1][y] = *reinterpret_cast<const v4i *>(Bs + (wn * 128 + y * 32) * kBK + foff1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int x = 1; x < 4; ++x) mfma_row(0, x);
+#pragma unroll
+            for (int x = 0; x < 4; ++x) mfma_row(1, x);
         }
         __syncthreads();   // no stage is read any more: the ring becomes the tile T[256][256] (uint16)
         // lane holds column (lane & 31) and rows 8*(r/4) + 4*(lane/32) + r%4 of each 32 x 32 block;
