@@ -236,13 +236,20 @@ def main():
         "success_rate": float(np.mean(ok)),
         "n_boundary_pairs_mean": float(np.mean([r.n_boundary_pairs for r in res])),
     }
-    if args.learned and os.path.exists(WEIGHTS) and args.workload == "indoor_n5000":
+    if args.learned and os.path.exists(WEIGHTS) and args.workload in ("indoor_n5000", "outdoor16"):
         from paper_2507_01439_amd import eval_learned
-        lreg = T.Registrar(max_n=5000, max_batch=1, max_k1=1000, max_k2=2)
+        if args.workload == "indoor_n5000":   # the hard slice (0.5-1 % inliers)
+            lreg = T.Registrar(max_n=5000, max_batch=1, max_k1=1000, max_k2=2)
+            _, pairs = eval_learned.held_out(0, 32)
+            sweep, ref = (32, 125, 250, 500, 1000), 1000
+        else:                                 # the 16 outdoor pairs, scorer trained on indoor pairs
+            lreg = T.Registrar(max_n=cfg.n, max_batch=1, max_k1=cfg.k1, max_k2=2)
+            pairs = groups[0]
+            sweep, ref = (125, 250, 500, 1000, 2500), cfg.k1
         with open(WEIGHTS, "rb") as f:
             T.tr_scorer_load(lreg.h, f.read())
-        _, hard = eval_learned.held_out(0, 32)
-        line["learned_vs_plain"] = eval_learned.compare(lreg, torch, hard, k1_sweep=(32, 125, 250, 500, 1000))
+        line["learned_vs_plain"] = eval_learned.compare(lreg, torch, pairs, k1_sweep=sweep, ref_k1=ref)
+        lreg.close()
         lreg.close()
     if args.cpu_budget > 0 and args.workload in ("indoor_n5000", "indoor_n1000"):
         line["cpu_baseline"] = cpu_baseline([g[0] for g in groups], cfg, args.cpu_budget)
