@@ -402,12 +402,29 @@ __device__ void select_pair(const Work &w, int b)
         w.out[b] = r;
     }
     if (w.masks && d.n > 0) {
+        // eight matches per thread: their loads are all issued before any residual is formed
         const float th2 = w.theta * w.theta;
-        for (int k = tid; k < d.n; k += 256) {
-            const int64_t g = d.pt_off + k;
-            const bool in = hbest >= 0 && residual2(ps, w.src[3 * g], w.src[3 * g + 1], w.src[3 * g + 2], w.dst[3 * g],
-                                                    w.dst[3 * g + 1], w.dst[3 * g + 2]) <= th2;
-            w.masks[g] = in ? 1 : 0;
+        constexpr int kM = 8;
+        for (int k0 = tid; k0 < d.n; k0 += 256 * kM) {
+            float x[kM][3], y[kM][3];
+#pragma unroll
+            for (int m = 0; m < kM; ++m) {
+                const int64_t g = d.pt_off + min(k0 + 256 * m, d.n - 1);
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    x[m][f] = w.src[3 * g + f];
+                    y[m][f] = w.dst[3 * g + f];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < kM; ++m) {
+                const int k = k0 + 256 * m;
+                if (k < d.n) {
+                    const bool in = hbest >= 0 &&
+                                    residual2(ps, x[m][0], x[m][1], x[m][2], y[m][0], y[m][1], y[m][2]) <= th2;
+                    w.masks[d.pt_off + k] = in ? 1 : 0;
+                }
+            }
         }
     }
 }
@@ -476,8 +493,10 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                 for (int k = 0; k < 12; ++k) ps[u][k] = pose_l[hl][k];
             }
             int cu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int k0 = tid; k0 < d.n; k0 += 1024) {   // four matches per thread in flight
-                float x[4][3], y[4][3];
+            // four matches per thread per step; the next step's loads are issued before this
+            // step's residuals are formed
+            float x[4][3], y[4][3];
+            auto load4 = [&](int k0) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const int64_t gi = d.pt_off + min(k0 + 256 * m, d.n - 1);
@@ -487,12 +506,25 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                         y[m][f] = w.dst[3 * gi + f];
                     }
                 }
+            };
+            load4(tid);
+            for (int k0 = tid; k0 < d.n; k0 += 1024) {
+                float cx[4][3], cy[4][3];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        cx[m][f] = x[m][f];
+                        cy[m][f] = y[m][f];
+                    }
+                if (k0 + 1024 < d.n) load4(k0 + 1024);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
                     const bool in = k0 + 256 * m < d.n;
 #pragma unroll
                     for (int u = 0; u < 8; ++u)
-                        cu[u] += in && residual2(ps[u], x[m][0], x[m][1], x[m][2], y[m][0], y[m][1], y[m][2]) <= th2;
+                        cu[u] += in &&
+                                 residual2(ps[u], cx[m][0], cx[m][1], cx[m][2], cy[m][0], cy[m][1], cy[m][2]) <= th2;
                 }
             }
 #pragma unroll
