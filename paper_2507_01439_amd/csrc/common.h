@@ -69,7 +69,8 @@ struct Work {
     float tau, theta;
     uint8_t *C;               // C arena
     uint16_t *G;              // G arena
-    int32_t *ghist;           // max_batch x kHistGroups x max_n weight histograms (filled by the SC2 epilogue)
+    int32_t *ghist;           // max_batch x kHistGroups x hist_stride weight histograms (filled by the SC2 epilogue)
+    int32_t hist_stride;      // max_n rounded up to 8 (16-byte aligned copies)
     int32_t *rowmax;          // max_batch x max_n: max_{j>i} G_ij (filled by the SC2 epilogue)
     int32_t *cnt_part;        // per compatibility work item: (boundary pairs, edges, non-finite input)
     int32_t *rowcnt;          // max_batch x max_n x 2 (count > alpha, count == alpha)

@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         if (diag) {   // the diagonal tiles clear this pair's histogram copies and row maxima for their 64 rows
             for (int k = tid; k < kHistGroups * 64; k += 256) {
                 const int i = bi * kCompatTile + (k & 63);
-                if (i < d.n) w.ghist[((int64_t)b * kHistGroups + (k >> 6)) * w.max_n + i] = 0;
+                if (i < d.n) w.ghist[((int64_t)b * kHistGroups + (k >> 6)) * w.hist_stride + i] = 0;
             }
             if (tid < 64 && bi * kCompatTile + tid < d.n) {
                 const int64_t ri = (int64_t)b * w.max_n + bi * kCompatTile + tid;
@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 }
             }
         __syncthreads();
-        int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + local % kHistGroups) * w.max_n;
+        int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + local % kHistGroups) * w.hist_stride;
         int32_t *rowmax = w.rowmax + (int64_t)b * w.max_n;
         int32_t *rstat = w.rowstat + (int64_t)b * w.max_n * 20;
         uint16_t *Gb = w.G + d.g_off;

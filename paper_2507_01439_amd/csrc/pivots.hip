@@ -141,21 +141,25 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     const PairDesc d = pair_desc(w, b);
     const int64_t K = d.kpiv;
     if (K <= 0) return;
-    const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.max_n;
-    // the 16 copies of four bins per thread are loaded before any is summed (the pass is latency-bound)
-    for (int v0 = threadIdx.x; v0 < d.n; v0 += 4096) {
-        int32_t c[4] = {0, 0, 0, 0};
+    const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.hist_stride;
+    // four consecutive bins per thread: one 16-byte load from each of the 16 copies, all issued
+    // before any is summed (the pass is latency-bound); bins at or past n are never written and are
+    // not summed (the copies are padded to a multiple of 8)
+    for (int v0 = 4 * threadIdx.x; v0 < d.n; v0 += 4 * 1024) {
+        int4 c[kHistGroups];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int v = v0 + 1024 * u;
-            if (v < d.n) {
+        for (int g = 0; g < kHistGroups; ++g) c[g] = *reinterpret_cast<const int4 *>(gh + (int64_t)g * w.hist_stride + v0);
+        int32_t sum[4] = {0, 0, 0, 0};
 #pragma unroll
-                for (int g = 0; g < kHistGroups; ++g) c[u] += gh[(int64_t)g * w.max_n + v];
-            }
+        for (int g = 0; g < kHistGroups; ++g) {
+            sum[0] += c[g].x;
+            sum[1] += c[g].y;
+            sum[2] += c[g].z;
+            sum[3] += c[g].w;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (v0 + 1024 * u < d.n) hs[v0 + 1024 * u] = c[u];
+            if (v0 + u < d.n) hs[v0 + u] = sum[u];
     }
     __syncthreads();
     const int nb = d.n - 1;                     // bins w = 1 .. n-1, walked from the top

@@ -157,6 +157,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.C = h->C;
     w.G = h->G;
     w.ghist = h->ghist;
+    w.hist_stride = (h->max_n + 7) & ~7;
     w.rowmax = h->rowmax;
     w.cnt_part = h->cnt_part;
     w.rowcnt = h->rowcnt;
@@ -362,7 +363,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->pre, (size_t)kNumPrefix * h->pre_stride));
     A(alloc(h, &h->C, B * nn / 2));   // packed E2M1, two entries per byte
     A(alloc(h, &h->G, B * nn));
-    A(alloc(h, &h->ghist, B * kHistGroups * max_n));
+    A(alloc(h, &h->ghist, B * kHistGroups * (size_t)((max_n + 7) & ~7)));
     A(alloc(h, &h->rowmax, B * max_n));
     {
         const size_t nb64 = h->npad_max / kCompatTile;
