@@ -71,6 +71,9 @@ def _declare(L):
     L.tro_mask.argtypes = [_f32p, _f32p, I, _f32p, ct.c_float, _u8p]
     L.tro_select.argtypes = [_i32p, I]
     L.tro_select.restype = I
+    L.tro_score_metric.argtypes = [_f32p, _f32p, I, _f32p, _i32p, I, ct.c_float, I, _f32p]
+    L.tro_select_score.argtypes = [_f32p, I]
+    L.tro_select_score.restype = I
     L.tro_register.argtypes = [_f32p, _f32p, I, ct.POINTER(Params), ct.POINTER(Result), ct.c_void_p]
     L.tro_features.argtypes = [_f32p, _f32p, I, ct.c_float, _u8p, _i32p, _f64p]
     L.tro_mlp_fwd.argtypes = [_f64p, I] + [_f64p] * 6 + [_f64p]
@@ -173,6 +176,25 @@ def mask(X, Y, pose, theta):
 def select(IN):
     IN = np.ascontiguousarray(IN, dtype=np.int32)
     return int(lib().tro_select(IN, IN.shape[0]))
+
+
+METRIC_MAE, METRIC_MSE = 1, 2
+
+
+def score_metric(X, Y, poses, valid, theta, metric):
+    """Error-based hypothesis scores (MAE or MSE form; larger is better, -1 if invalid)."""
+    X, Y = _pts(X), _pts(Y)
+    poses = np.ascontiguousarray(poses, dtype=np.float32).reshape(-1, 12)
+    valid = np.ascontiguousarray(valid, dtype=np.int32)
+    S = np.empty(poses.shape[0], np.float32)
+    _check(lib().tro_score_metric(X, Y, X.shape[0], poses, valid, poses.shape[0], float(theta), int(metric), S),
+           "score_metric")
+    return S
+
+
+def select_score(S):
+    S = np.ascontiguousarray(S, dtype=np.float32)
+    return int(lib().tro_select_score(S, S.shape[0]))
 
 
 def register(X, Y, tau, theta, k1, k2, graph=0):

@@ -402,6 +402,42 @@ int32_t tro_select(const int32_t *IN, int32_t H)
     return best;
 }
 
+/* Error-based hypothesis scores (the ranking study of the supplementary
+ * material, Table 6: hypotheses ranked by mean absolute / mean squared error
+ * instead of the inlier number). Reading: over the inliers of Eq. 9 (the same
+ * float32 test r^2 <= theta^2), with e = sqrt(r^2) (float32, correctly rounded)
+ * and u = (theta - e) / theta in float32, the MAE score is the sum of u and the
+ * MSE score the sum of u * u (float32 products), summed in float64 and rounded
+ * to float32. Larger is better: more inliers, and closer ones. An invalid
+ * hypothesis scores -1. metric: 1 = MAE, 2 = MSE. */
+int tro_score_metric(const float *X, const float *Y, int32_t n, const float *poses,
+                     const int32_t *valid, int32_t H, float theta, int32_t metric, float *S)
+{
+    if (!X || !Y || !poses || !valid || !S || n < 0 || H < 0 || (metric != 1 && metric != 2)) return -1;
+    const float th2 = theta * theta;
+    for (int32_t h = 0; h < H; ++h) {
+        if (!valid[h]) { S[h] = -1.0f; continue; }
+        double acc = 0.0;
+        for (int32_t k = 0; k < n; ++k) {
+            const float r2 = residual2(poses + 12 * (int64_t)h, X + 3 * (int64_t)k, Y + 3 * (int64_t)k);
+            if (!(r2 <= th2)) continue;
+            const float u = (theta - sqrtf(r2)) / theta;
+            acc += metric == 1 ? (double)u : (double)(u * u);
+        }
+        S[h] = (float)acc;
+    }
+    return 0;
+}
+
+/* The largest score (lowest h among equal ones); -1 when every score is negative. */
+int32_t tro_select_score(const float *S, int32_t H)
+{
+    int32_t best = -1;
+    for (int32_t h = 0; h < H; ++h)
+        if (S[h] >= 0.0f && (best < 0 || S[h] > S[best])) best = h;
+    return best;
+}
+
 /* ------------------------------------------------------------------ */
 /* Whole path                                                          */
 /* ------------------------------------------------------------------ */

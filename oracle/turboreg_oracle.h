@@ -67,6 +67,11 @@ int tro_mask(const float *X, const float *Y, int32_t n, const float *pose, float
 
 /* argmax_h IN_h, lowest h among ties; -1 if no IN_h >= 0. */
 int32_t tro_select(const int32_t *IN, int32_t H);
+/* Error-based scores of valid hypotheses (metric 1 = MAE, 2 = MSE; larger is better, -1 if
+ * invalid) and their argmax (lowest h on ties, -1 if none is valid). */
+int tro_score_metric(const float *X, const float *Y, int32_t n, const float *poses,
+                     const int32_t *valid, int32_t H, float theta, int32_t metric, float *S);
+int32_t tro_select_score(const float *S, int32_t H);
 
 typedef struct {
     float tau, theta;

@@ -515,6 +515,47 @@ def test_bf16_rounding_known_values():
     assert math.isnan(oracle.bf16_round(float("nan")))
 
 
+def test_error_scores_hand_example():
+    # identity pose, residuals 0, 0.25, 0.5, 0.75 and theta = 0.5 (all exact in binary):
+    # inliers r <= theta are the first three; u = (theta - r) / theta = 1, 0.5, 0
+    X = np.zeros((4, 3), np.float32)
+    Y = np.array([[0, 0, 0], [0.25, 0, 0], [0, 0.5, 0], [0, 0, 0.75]], np.float32)
+    pose = np.array([[1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0]], np.float32)
+    valid = np.ones(1, np.int32)
+    assert oracle.score(X, Y, pose, valid, 0.5)[0] == 3
+    assert oracle.score_metric(X, Y, pose, valid, 0.5, oracle.METRIC_MAE)[0] == 1.5
+    assert oracle.score_metric(X, Y, pose, valid, 0.5, oracle.METRIC_MSE)[0] == 1.25
+    # a translation that moves every target onto its source scores n: every u is exactly 1
+    pose_t = pose.copy()
+    pose_t[0, 9:] = [0.0, 0.0, 0.0]
+    Z = np.random.default_rng(1).random((7, 3)).astype(np.float32)
+    for m in (oracle.METRIC_MAE, oracle.METRIC_MSE):
+        assert oracle.score_metric(Z, Z, pose_t, valid, 0.1, m)[0] == 7.0
+
+
+def test_error_scores_order_and_bounds():
+    rng = np.random.default_rng(9)
+    X = rng.random((300, 3)).astype(np.float32)
+    R = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    R *= np.sign(np.linalg.det(R))
+    Y = (X @ R.T + 0.3 + rng.normal(0, 0.02, X.shape)).astype(np.float32)
+    poses = np.zeros((5, 12), np.float32)
+    for h in range(5):
+        poses[h, :9] = R.reshape(9) if h < 4 else np.eye(3).reshape(9)
+        poses[h, 9:] = 0.3 + 0.01 * h
+    valid = np.array([1, 1, 0, 1, 1], np.int32)
+    IN = oracle.score(X, Y, poses, valid, 0.05)
+    mae = oracle.score_metric(X, Y, poses, valid, 0.05, oracle.METRIC_MAE)
+    mse = oracle.score_metric(X, Y, poses, valid, 0.05, oracle.METRIC_MSE)
+    assert mae[2] == -1 and mse[2] == -1
+    ok = valid == 1
+    assert (mse[ok] <= mae[ok]).all() and (mae[ok] <= IN[ok]).all() and (mse[ok] >= 0).all()
+    # the pose closest to the data (h = 0) wins under both error scores; the selection is the argmax
+    assert oracle.select_score(mae) == 0 and oracle.select_score(mse) == 0
+    assert oracle.select_score(np.array([-1, 2.0, 2.0, 1.0], np.float32)) == 1
+    assert oracle.select_score(np.array([-1, -1], np.float32)) == -1
+
+
 def test_learned_pivots_order_and_fallback():
     P = np.array([[0, 1, 9], [2, 3, 8], [4, 5, 8], [6, 7, 1]], np.int32)
     s = np.array([0, 0, 1, 1, 5, 5, 0.5, 0.5], np.float32)
