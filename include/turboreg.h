@@ -51,8 +51,15 @@ enum { TR_GRAPH_O2 = 0, TR_GRAPH_SC2 = 1 };          /* Definition 2 / undirecte
 enum { TR_PIVOTS_PLAIN = 0, TR_PIVOTS_LEARNED = 1 };
 enum {
     TR_FLAG_PROFILE = 1u,       /* record per-stage HIP events; read with tr_stage_times          */
-    TR_FLAG_PROFILE_SC2 = 2u    /* record only the two events around the SC2 kernel (its launch  */
+    TR_FLAG_PROFILE_SC2 = 2u,   /* record only the two events around the SC2 kernel (its launch  */
                                 /* duration, least perturbation); ignored with TR_FLAG_PROFILE   */
+    /* Selection by an error-based score instead of the inlier number (the ranking study of the
+     * paper's supplementary Table 6). Over the inliers of Eq. 9 (r^2 <= theta^2), with
+     * e = sqrt(r^2) and u = max(0, (theta - e) / theta) in float32, the score is the sum of u (MAE form)
+     * or of u*u (MSE form), summed in float32; the largest score wins (lowest h on ties).
+     * best_inliers is still the selected hypothesis's inlier number. At most one of the two. */
+    TR_FLAG_RANK_MAE = 4u,
+    TR_FLAG_RANK_MSE = 8u
 };
 
 typedef struct {
@@ -193,7 +200,9 @@ enum {
                              are endpoints of the plain pool's pivots are written, the
                              others keep older values)                                 */
     TR_TAP_SCORES = 7,    /* N float32 learned scores (learned mode; same rows as above)  */
-    TR_TAP_PLAIN_PIVOTS = 8 /* pool x 3 int32 plain pivots before the learned reorder  */
+    TR_TAP_PLAIN_PIVOTS = 8, /* pool x 3 int32 plain pivots before the learned reorder */
+    TR_TAP_RANK_SCORES = 9  /* H float32 error-based scores (TR_FLAG_RANK_* calls only), -1
+                               for an invalid hypothesis                                 */
 };
 
 /* Synchronise the handle's last stream and copy intermediate `tap` of pair

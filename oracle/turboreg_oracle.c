@@ -406,7 +406,7 @@ int32_t tro_select(const int32_t *IN, int32_t H)
  * material, Table 6: hypotheses ranked by mean absolute / mean squared error
  * instead of the inlier number). Reading: over the inliers of Eq. 9 (the same
  * float32 test r^2 <= theta^2), with e = sqrt(r^2) (float32, correctly rounded)
- * and u = (theta - e) / theta in float32, the MAE score is the sum of u and the
+ * and u = max(0, (theta - e) / theta) in float32, the MAE score is the sum of u and the
  * MSE score the sum of u * u (float32 products), summed in float64 and rounded
  * to float32. Larger is better: more inliers, and closer ones. An invalid
  * hypothesis scores -1. metric: 1 = MAE, 2 = MSE. */
@@ -421,7 +421,8 @@ int tro_score_metric(const float *X, const float *Y, int32_t n, const float *pos
         for (int32_t k = 0; k < n; ++k) {
             const float r2 = residual2(poses + 12 * (int64_t)h, X + 3 * (int64_t)k, Y + 3 * (int64_t)k);
             if (!(r2 <= th2)) continue;
-            const float u = (theta - sqrtf(r2)) / theta;
+            float u = (theta - sqrtf(r2)) / theta;
+            if (u < 0.0f) u = 0.0f;   /* r^2 <= theta^2 can still leave e one ulp above theta */
             acc += metric == 1 ? (double)u : (double)(u * u);
         }
         S[h] = (float)acc;

@@ -86,6 +86,8 @@ struct Work {
     int32_t *cliques;         // max_batch x h_cap x 3
     float *poses;             // max_batch x h_cap x 12
     int32_t *inl;             // max_batch x h_cap
+    float *gscore;            // max_batch x h_cap error-based scores (metric != 0)
+    int32_t metric;           // hypothesis ranking: 0 inlier number, 1 MAE form, 2 MSE form
     int32_t h_cap;
     int32_t *rowstat;         // max_batch x max_n x 20 feature accumulators (learned mode)
     int32_t *mark;            // max_batch x max_n: row claimed by a candidate-feature workgroup

@@ -386,7 +386,10 @@ __device__ void select_pair(const Work &w, int b)
         tr_result r;
         for (int k = 0; k < 9; ++k) r.R[k] = ps[k];
         for (int k = 0; k < 3; ++k) r.t[k] = ps[9 + k];
-        r.best_inliers = hbest >= 0 ? (int32_t)(best >> 32) - 1 : 0;
+        r.best_inliers = hbest < 0 ? 0
+                         : w.metric ? __hip_atomic_load(&w.inl[(int64_t)b * w.h_cap + hbest], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT)
+                                    : (int32_t)(best >> 32) - 1;
         r.best_hyp = hbest;
         r.n_valid_hyp = nvalid;
         int status = TR_OK;
@@ -430,6 +433,24 @@ __device__ void select_pair(const Work &w, int b)
 }
 
 // Sum over the 64 lanes (DPP), valid in every lane.
+template <int CTRL, int RMASK>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RMASK, 0xf, false));
+}
+
+// Sum over the 64 lanes (DPP, a fixed order), valid in every lane.
+__device__ __forceinline__ float wave_total_f(float v)
+{
+    v += dpp_f<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_f<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_f<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_f<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_f<0x142, 0xa>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_f<0x143, 0xc>(v);   // row_bcast:31 into rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ int wave_total(int v)
 {
     v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
@@ -456,11 +477,12 @@ __device__ __forceinline__ void store_agent(float *p, float v)
 // atomics. IN and the poses are stored at device scope and each item folds
 // its best (IN, h) and valid count into the pair's state; the workgroup that
 // finishes a pair's last item (atomic ticket, no waiting) selects the result.
-template <int KMAX>
+template <int KMAX, int METRIC>
 __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
 {
     __shared__ float pose_l[16 * TR_MAX_K2][12];
     __shared__ int32_t valid_l[16 * TR_MAX_K2], tot_l[16 * TR_MAX_K2];
+    __shared__ float sc_l[4][16 * TR_MAX_K2];   // per-wave error-score sums (METRIC only)
     __shared__ int32_t last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ipp = (w.k1 + ppw - 1) / ppw, total = B * ipp;
@@ -493,6 +515,7 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                 for (int k = 0; k < 12; ++k) ps[u][k] = pose_l[hl][k];
             }
             int cu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            float su[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // error-based scores (METRIC only)
             // four matches per thread per step; the next step's loads are issued before this
             // step's residuals are formed
             float x[4][3], y[4][3];
@@ -522,15 +545,25 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                 for (int m = 0; m < 4; ++m) {
                     const bool in = k0 + 256 * m < d.n;
 #pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        cu[u] += in &&
-                                 residual2(ps[u], cx[m][0], cx[m][1], cx[m][2], cy[m][0], cy[m][1], cy[m][2]) <= th2;
+                    for (int u = 0; u < 8; ++u) {
+                        const float r2 = residual2(ps[u], cx[m][0], cx[m][1], cx[m][2], cy[m][0], cy[m][1], cy[m][2]);
+                        const bool hit = in && r2 <= th2;
+                        cu[u] += hit;
+                        if (METRIC) {
+                            const float c = fmaxf((w.theta - __builtin_sqrtf(r2)) / w.theta, 0.0f);
+                            su[u] += hit ? (METRIC == 1 ? c : c * c) : 0.0f;
+                        }
+                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int t = wave_total(cu[u]);
                 if (lane == 0 && t && h0 + u < nloc) atomicAdd(&tot_l[h0 + u], t);
+                if (METRIC) {   // per-wave sums, added in wave order below (deterministic)
+                    const float f = wave_total_f(su[u]);
+                    if (lane == 0 && h0 + u < nloc) sc_l[wv][h0 + u] = f;
+                }
             }
         }
         __syncthreads();
@@ -544,8 +577,14 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                                    __HIP_MEMORY_SCOPE_AGENT);
 #pragma unroll
                 for (int k = 0; k < 12; ++k) store_agent(w.poses + slot * 12 + k, pose_l[tid][k]);
+                uint32_t primary = (uint32_t)(tot_l[tid] + 1);
+                if (METRIC) {
+                    const float sc = ((sc_l[0][tid] + sc_l[1][tid]) + sc_l[2][tid]) + sc_l[3][tid];
+                    store_agent(w.gscore + slot, valid_l[tid] ? sc : -1.0f);
+                    primary = __float_as_uint(sc) + 1u;   // sc >= 0: the bits order like the values
+                }
                 if (valid_l[tid]) {
-                    key = ((uint64_t)(tot_l[tid] + 1) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
+                    key = ((uint64_t)primary << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)h);
                     nv = 1;
                 }
             }
@@ -582,8 +621,17 @@ hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s)
     if (ppw < 4 || ppw > 16 || ppw % 4) return hipErrorInvalidValue;
     const int total = B * ((w.k1 + ppw - 1) / ppw);
     grid = max(1, min(total, grid));
-    if (w.k2 <= 2) hipLaunchKernelGGL(k_hyp<2>, dim3(grid), dim3(256), 0, s, w, B, ppw);
-    else hipLaunchKernelGGL(k_hyp<TR_MAX_K2>, dim3(grid), dim3(256), 0, s, w, B, ppw);
+    const bool small = w.k2 <= 2;
+    if (w.metric == 1) {
+        if (small) hipLaunchKernelGGL((k_hyp<2, 1>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 1>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+    } else if (w.metric == 2) {
+        if (small) hipLaunchKernelGGL((k_hyp<2, 2>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 2>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+    } else {
+        if (small) hipLaunchKernelGGL((k_hyp<2, 0>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 0>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+    }
     return hipGetLastError();
 }
 

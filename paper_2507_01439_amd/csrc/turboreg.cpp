@@ -48,7 +48,7 @@ struct tr_handle {
     int32_t *ghist = nullptr, *rowmax = nullptr, *cnt_part = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
     uint64_t *cand = nullptr, *rowseg = nullptr;
     int32_t *pivots_plain = nullptr, *pivots = nullptr, *cliques = nullptr, *inl = nullptr;
-    float *poses = nullptr;
+    float *poses = nullptr, *gscore = nullptr;
     int32_t *rowstat = nullptr, *mark = nullptr;
     uint16_t *feat = nullptr;
     float *scores = nullptr;
@@ -172,6 +172,8 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.cliques = h->cliques;
     w.poses = h->poses;
     w.inl = h->inl;
+    w.gscore = h->gscore;
+    w.metric = (p.flags & TR_FLAG_RANK_MAE) ? 1 : (p.flags & TR_FLAG_RANK_MSE) ? 2 : 0;
     w.h_cap = h->h_cap;
     w.rowstat = h->rowstat;
     w.mark = h->mark;
@@ -189,6 +191,7 @@ tr_status check_params(tr_handle *h, const tr_params *p)
     if (!p) return TR_ERR_INVALID_ARG;
     if (!(p->tau >= 0.0f) || !std::isfinite(p->tau)) return TR_ERR_INVALID_ARG;
     if (!(p->inlier_thresh >= 0.0f) || !std::isfinite(p->inlier_thresh)) return TR_ERR_INVALID_ARG;
+    if ((p->flags & TR_FLAG_RANK_MAE) && (p->flags & TR_FLAG_RANK_MSE)) return TR_ERR_INVALID_ARG;
     if (p->k1 < 1 || p->k2 < 1 || p->k2 > TR_MAX_K2) return TR_ERR_INVALID_ARG;
     if (p->graph != TR_GRAPH_O2 && p->graph != TR_GRAPH_SC2) return TR_ERR_INVALID_ARG;
     if (p->pivot_mode != TR_PIVOTS_PLAIN && p->pivot_mode != TR_PIVOTS_LEARNED) return TR_ERR_INVALID_ARG;
@@ -378,6 +381,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     A(alloc(h, &h->cliques, B * h->h_cap * 3));
     A(alloc(h, &h->poses, B * h->h_cap * 12));
     A(alloc(h, &h->inl, B * h->h_cap));
+    A(alloc(h, &h->gscore, B * h->h_cap));
     A(alloc(h, &h->rowstat, B * max_n * 20));
     A(alloc(h, &h->mark, B * max_n));
     A(alloc(h, &h->feat, B * max_n * 19));
@@ -636,6 +640,8 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
         need = (size_t)w.H * 48; srcp = h->poses + (size_t)pair * h->h_cap * 12; break;
     case TR_TAP_IN:
         need = (size_t)w.H * 4; srcp = h->inl + (size_t)pair * h->h_cap; break;
+    case TR_TAP_RANK_SCORES:
+        need = (size_t)w.H * 4; srcp = h->gscore + (size_t)pair * h->h_cap; break;
     case TR_TAP_FEATURES:
         need = n * 19 * 2; srcp = h->feat + (size_t)pair * h->max_n * 19; break;
     case TR_TAP_SCORES:

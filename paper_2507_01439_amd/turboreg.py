@@ -19,11 +19,11 @@ TR_OK, TR_ERR_INVALID_ARG, TR_ERR_NONFINITE, TR_ERR_NO_HYPOTHESIS = 0, 1, 2, 3
 TR_ERR_WORKSPACE, TR_ERR_HIP, TR_WARN_SCORER_FALLBACK, TR_ERR_NO_SCORER, TR_ERR_BAD_BLOB = 4, 5, 6, 7, 8
 TR_GRAPH_O2, TR_GRAPH_SC2 = 0, 1
 TR_PIVOTS_PLAIN, TR_PIVOTS_LEARNED = 0, 1
-TR_FLAG_PROFILE, TR_FLAG_PROFILE_SC2 = 1, 2
+TR_FLAG_PROFILE, TR_FLAG_PROFILE_SC2, TR_FLAG_RANK_MAE, TR_FLAG_RANK_MSE = 1, 2, 4, 8
 TR_MAX_K2 = 8
 TR_MLP_NPARAM = 5505
 (TR_TAP_C, TR_TAP_G, TR_TAP_PIVOTS, TR_TAP_CLIQUES, TR_TAP_POSES, TR_TAP_IN, TR_TAP_FEATURES,
- TR_TAP_SCORES, TR_TAP_PLAIN_PIVOTS) = range(9)
+ TR_TAP_SCORES, TR_TAP_PLAIN_PIVOTS, TR_TAP_RANK_SCORES) = range(10)
 STAGES = ("plan", "compat", "sc2", "pivots", "learned", "cliques", "kabsch", "score", "select")
 TR_NUM_STAGES = len(STAGES)
 
@@ -215,7 +215,8 @@ def tr_train_step(h, feat, labels, m, lr, loss=None):
 
 _TAP_DTYPES = {TR_TAP_C: (np.uint8, "nn"), TR_TAP_G: (np.uint16, "nn"), TR_TAP_PIVOTS: (np.int32, 3),
                TR_TAP_PLAIN_PIVOTS: (np.int32, 3), TR_TAP_CLIQUES: (np.int32, 3), TR_TAP_POSES: (np.float32, 12),
-               TR_TAP_IN: (np.int32, 1), TR_TAP_FEATURES: (np.uint16, 19), TR_TAP_SCORES: (np.float32, 1)}
+               TR_TAP_IN: (np.int32, 1), TR_TAP_FEATURES: (np.uint16, 19), TR_TAP_SCORES: (np.float32, 1),
+               TR_TAP_RANK_SCORES: (np.float32, 1)}
 
 
 def tr_debug_copy(h, tap, pair=0):
