@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time (0 = skip)")
     ap.add_argument("--learned", action="store_true", help="add the learned-vs-plain comparison (needs weights)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--ranking", action="store_true",
+                    help="add ranking-based recalls (IN / MSE / MAE ranking) on 32 low-inlier N=5000 pairs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times (a kernel of known traffic for "
                          "scaling hardware byte counters)")
@@ -236,6 +238,18 @@ def main():
         "success_rate": float(np.mean(ok)),
         "n_boundary_pairs_mean": float(np.mean([r.n_boundary_pairs for r in res])),
     }
+    if args.ranking:
+        from paper_2507_01439_amd import diagnostics
+        base = synth.CONFIGS["indoor_n5000"]
+        rng = np.random.default_rng(17)
+        rpairs = [synth.make_pair(base.replace(inlier_ratio=float(q)), synth.pair_seed(8, b))
+                  for b, q in enumerate(rng.uniform(0.005, 0.02, size=32))]
+        rreg = T.Registrar(max_n=base.n, max_batch=1, max_k1=base.k1, max_k2=2)
+        line["ranking_recalls"] = {"pairs": 32, "inlier_ratio": [0.005, 0.02], "k1": base.k1,
+                                   "table": {name: diagnostics.ranking_recalls(rreg, torch, rpairs, base.k1,
+                                                                               ranking=name)
+                                             for name in diagnostics.RANKINGS}}
+        rreg.close()
     if args.learned and os.path.exists(WEIGHTS) and args.workload in ("indoor_n5000", "outdoor16"):
         from paper_2507_01439_amd import eval_learned
         if args.workload == "indoor_n5000":   # the hard slice (0.5-1 % inliers)

@@ -114,6 +114,17 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst,
                             const tr_params *p, tr_result *out_dev, uint8_t *masks_dev,
                             void *stream);
 
+/* Score caller-given poses against one pair (N x 3 src, dst device arrays): for each of the P
+ * poses (P x 12 float32 device array, R row-major then t) its inlier number (Eq. 9, the same
+ * float32 test as the registration) into in_dev (P int32), and for metric 1 (MAE form) or 2
+ * (MSE form) its error-based score into score_dev (P float32; may be NULL for metric 0), both
+ * computed in the same arithmetic and order as the registration's hypothesis scoring, so a
+ * hypothesis pose scores the same bits. For evaluating external poses (a ground-truth
+ * transformation, poses from another method). TR_ERR_INVALID_ARG for n < 1, P < 0, a negative
+ * or non-finite theta, metric outside 0..2 or a missing score buffer. */
+tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32_t n, const float *poses_dev,
+                         int32_t P, float theta, int32_t metric, int32_t *in_dev, float *score_dev, void *stream);
+
 /* ---- launch configuration and autotuner ----
  * Calls are grouped by shape: the number of 256-row tiles of their largest
  * pair, round_up(max_n, 256) / 256, and the batch size B (1 for tr_register).

@@ -607,7 +607,81 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
     }
 }
 
+// Inlier numbers (Eq. 9) and, for metric 1 / 2, the error-based scores of
+// caller-given poses against one pair's matches: eight poses per workgroup,
+// the matches strided over the 256 threads and every sum formed in the same
+// order as in k_hyp, so a pose scores the same bits here as there.
+__global__ void __launch_bounds__(256) k_score_poses(const float *src, const float *dst, int n, const float *poses,
+                                                     int P, float theta, int metric, int32_t *in_out,
+                                                     float *score_out)
+{
+    __shared__ int32_t cnt_l[4][8];
+    __shared__ float sum_l[4][8];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const float th2 = theta * theta;
+    for (int p0 = blockIdx.x * 8; p0 < P; p0 += gridDim.x * 8) {
+        float ps[8][12];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int k = 0; k < 12; ++k) ps[u][k] = poses[(int64_t)min(p0 + u, P - 1) * 12 + k];
+        int cu[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        float su[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k0 = tid; k0 < n; k0 += 1024) {
+            float x[4][3], y[4][3];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int64_t gi = min(k0 + 256 * m, n - 1);
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    x[m][f] = src[3 * gi + f];
+                    y[m][f] = dst[3 * gi + f];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const bool in = k0 + 256 * m < n;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float r2 = residual2(ps[u], x[m][0], x[m][1], x[m][2], y[m][0], y[m][1], y[m][2]);
+                    const bool hit = in && r2 <= th2;
+                    cu[u] += hit;
+                    if (metric) {
+                        const float c = fmaxf((theta - __builtin_sqrtf(r2)) / theta, 0.0f);
+                        su[u] += hit ? (metric == 1 ? c : c * c) : 0.0f;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = wave_total(cu[u]);
+            const float f = wave_total_f(su[u]);
+            if (lane == 0) {
+                cnt_l[wv][u] = t;
+                sum_l[wv][u] = f;
+            }
+        }
+        __syncthreads();
+        if (tid < 8 && p0 + tid < P) {
+            in_out[p0 + tid] = cnt_l[0][tid] + cnt_l[1][tid] + cnt_l[2][tid] + cnt_l[3][tid];
+            if (metric && score_out)
+                score_out[p0 + tid] = ((sum_l[0][tid] + sum_l[1][tid]) + sum_l[2][tid]) + sum_l[3][tid];
+        }
+        __syncthreads();   // the LDS totals are the next group's
+    }
+}
+
 }  // namespace
+
+hipError_t launch_score_poses(const float *src, const float *dst, int n, const float *poses, int P, float theta,
+                              int metric, int32_t *in_out, float *score_out, int grid, hipStream_t s)
+{
+    grid = max(1, min(grid, (P + 7) / 8));
+    hipLaunchKernelGGL(k_score_poses, dim3(grid), dim3(256), 0, s, src, dst, n, poses, P, theta, metric, in_out,
+                       score_out);
+    return hipGetLastError();
+}
 
 hipError_t setup_hyp_kernels()
 {

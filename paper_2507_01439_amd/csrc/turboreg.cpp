@@ -487,6 +487,19 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     return TR_OK;
 }
 
+tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32_t n, const float *poses_dev,
+                         int32_t P, float theta, int32_t metric, int32_t *in_dev, float *score_dev, void *stream)
+{
+    if (!h || !src || !dst || !poses_dev || !in_dev || n < 1 || P < 0) return TR_ERR_INVALID_ARG;
+    if (!(theta >= 0.0f) || !std::isfinite(theta) || metric < 0 || metric > 2 || (metric && !score_dev))
+        return TR_ERR_INVALID_ARG;
+    if (P == 0) return TR_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    const hipError_t e = launch_score_poses(src, dst, n, poses_dev, P, theta, metric, in_dev, score_dev,
+                                            h->num_cus * 4, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TR_OK : TR_ERR_HIP;
+}
+
 tr_status tr_tuning_get(tr_handle *h, int32_t max_n, int32_t B, tr_tuning *out)
 {
     if (!h || !out || max_n < 3 || B < 1) return TR_ERR_INVALID_ARG;

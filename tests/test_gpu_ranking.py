@@ -117,3 +117,58 @@ def test_both_rankings_rejected(reg):
     with pytest.raises(T.TurboRegError) as e:
         run_single(reg, torch, p.src, p.dst, prm)
     assert e.value.status == T.TR_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("metric", [0, 1, 2])
+def test_score_poses_matches_registration_and_oracle(reg, metric):
+    cfg = synth.CONFIGS["indoor_n1000"].replace(n=1700, k1=300)
+    p = synth.make_pair(cfg, synth.pair_seed(7, 40))
+    flag = {0: 0, 1: T.TR_FLAG_RANK_MAE, 2: T.TR_FLAG_RANK_MSE}[metric]
+    prm = T.make_params(cfg.tau, cfg.theta, cfg.k1, cfg.k2, flags=flag)
+    run_single(reg, torch, p.src, p.dst, prm)
+    poses, IN = reg.debug(T.TR_TAP_POSES), reg.debug(T.TR_TAP_IN)
+    S = reg.debug(T.TR_TAP_RANK_SCORES) if metric else None
+    # the hypothesis poses and the generator's pose, scored by the entry point
+    R, t = np.asarray(p.R, np.float64), np.asarray(p.t, np.float64)
+    gt = np.concatenate([R.reshape(9), t]).astype(np.float32)[None]
+    allp = np.concatenate([poses, gt]).astype(np.float32)
+    P = allp.shape[0]
+    src, dst = to_dev(torch, p.src), to_dev(torch, p.dst)
+    pin = torch.full((P,), -7, dtype=torch.int32, device="cuda")
+    psc = torch.full((P,), -7.0, dtype=torch.float32, device="cuda")
+    T.tr_score_poses(reg.h, src, dst, cfg.n, to_dev(torch, allp), P, cfg.theta, metric, pin, psc if metric else None)
+    torch.cuda.synchronize()
+    pin, psc = pin.cpu().numpy(), psc.cpu().numpy()
+    ok = IN >= 0
+    assert np.array_equal(pin[:-1][ok], IN[ok])
+    if metric:
+        assert np.array_equal(psc[:-1][ok].view(np.uint32), S[ok].view(np.uint32))   # the same bits
+        so = oracle.score_metric(p.src, p.dst, gt, np.ones(1, np.int32), cfg.theta, metric)[0]
+        assert abs(psc[-1] - so) <= ATOL + RTOL * abs(so)
+    else:
+        assert np.all(psc == -7.0)   # untouched
+    assert pin[-1] == oracle.score(p.src, p.dst, gt, np.ones(1, np.int32), cfg.theta)[0]
+
+
+def test_score_poses_argument_errors(reg):
+    x = torch.zeros((5, 3), dtype=torch.float32, device="cuda")
+    poses = torch.zeros((2, 12), dtype=torch.float32, device="cuda")
+    out = torch.zeros(2, dtype=torch.int32, device="cuda")
+    sc = torch.zeros(2, dtype=torch.float32, device="cuda")
+    for args in [(0, 0.1, 0, sc), (5, 0.1, 3, sc), (5, 0.1, 1, None), (5, -1.0, 0, sc), (5, float("nan"), 0, sc)]:
+        n, th, m, s = args
+        with pytest.raises(T.TurboRegError) as e:
+            T.tr_score_poses(reg.h, x, x, n, poses, 2, th, m, out, s)
+        assert e.value.status == T.TR_ERR_INVALID_ARG
+    T.tr_score_poses(reg.h, x, x, 5, poses, 0, 0.1, 1, out, sc)   # no poses: nothing to do
+
+
+def test_ranking_recalls_on_generated_pairs(reg):
+    from paper_2507_01439_amd import diagnostics
+    base = synth.CONFIGS["indoor_n1000"].replace(n=1500, inlier_ratio=0.03)
+    pairs = [synth.make_pair(base, synth.pair_seed(7, 60 + b)) for b in range(4)]
+    for name in diagnostics.RANKINGS:
+        t = diagnostics.ranking_recalls(reg, torch, pairs, k1=300, ranking=name)
+        say(name, t)
+        assert all(0.0 <= v <= 1.0 for v in t.values())
+        assert t["TKRR@2"] >= t["RR"] and t["TKRR@50"] >= t["TKRR@5"] >= t["TKRR@3"] >= t["TKRR@2"]
