@@ -114,6 +114,15 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst,
                             const tr_params *p, tr_result *out_dev, uint8_t *masks_dev,
                             void *stream);
 
+/* Rigid fits of caller-given triplets of match indices (T x 3 int32 device array) of one pair
+ * (N x 3 src, dst device arrays), by the registration's own 3-point fit (Section 3.5: Horn's
+ * quaternion form in float64, rounded to float32): poses_dev receives T x 12 float32 (R
+ * row-major, then t), ok_dev T int32 (1 = a well-posed fit; 0 = degenerate triplet or an
+ * index outside [0, n), with the identity pose). For studies of the fits themselves, such as
+ * 3-point against larger-clique estimates. TR_ERR_INVALID_ARG for n < 3 or T < 0. */
+tr_status tr_fit_triplets(tr_handle *h, const float *src, const float *dst, int32_t n, const int32_t *triplets_dev,
+                          int32_t T, float *poses_dev, int32_t *ok_dev, void *stream);
+
 /* Score caller-given poses against one pair (N x 3 src, dst device arrays): for each of the P
  * poses (P x 12 float32 device array, R row-major then t) its inlier number (Eq. 9, the same
  * float32 test as the registration) into in_dev (P int32), and for metric 1 (MAE form) or 2

@@ -230,6 +230,8 @@ hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
 hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
 hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
 hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s);
+hipError_t launch_fit_triplets(const float *src, const float *dst, int n, const int32_t *tri, int T, float *poses,
+                               int32_t *ok, int grid, hipStream_t s);
 hipError_t launch_score_poses(const float *src, const float *dst, int n, const float *poses, int P, float theta,
                               int metric, int32_t *in_out, float *score_out, int grid, hipStream_t s);
 hipError_t setup_hyp_kernels();

@@ -672,7 +672,38 @@ __global__ void __launch_bounds__(256) k_score_poses(const float *src, const flo
     }
 }
 
+// One rigid fit (Section 3.5, the registration's fit_pose) per caller-given
+// triplet of match indices; a triplet with an index outside [0, n) or a
+// negative one gets the identity pose and ok = 0.
+__global__ void __launch_bounds__(256) k_fit_triplets(Work w, PairDesc d, const int32_t *tri, int T, float *poses,
+                                                      int32_t *ok)
+{
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
+        const int a = tri[3 * t], b = tri[3 * t + 1], c = tri[3 * t + 2];
+        float pose[12];
+        const bool in = a >= 0 && a < d.n && b >= 0 && b < d.n && c >= 0 && c < d.n;
+        const bool fit = fit_pose(w, d, in ? a : 0, in ? b : 0, in ? c : -1, pose);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) poses[(int64_t)t * 12 + k] = pose[k];
+        ok[t] = in && fit;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_fit_triplets(const float *src, const float *dst, int n, const int32_t *tri, int T, float *poses,
+                               int32_t *ok, int grid, hipStream_t s)
+{
+    Work w{};
+    w.src = src;
+    w.dst = dst;
+    PairDesc d{};
+    d.n = n;
+    d.pt_off = 0;
+    grid = max(1, min(grid, (T + 255) / 256));
+    hipLaunchKernelGGL(k_fit_triplets, dim3(grid), dim3(256), 0, s, w, d, tri, T, poses, ok);
+    return hipGetLastError();
+}
 
 hipError_t launch_score_poses(const float *src, const float *dst, int n, const float *poses, int P, float theta,
                               int metric, int32_t *in_out, float *score_out, int grid, hipStream_t s)

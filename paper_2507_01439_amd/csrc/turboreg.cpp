@@ -487,6 +487,17 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     return TR_OK;
 }
 
+tr_status tr_fit_triplets(tr_handle *h, const float *src, const float *dst, int32_t n, const int32_t *triplets_dev,
+                          int32_t T, float *poses_dev, int32_t *ok_dev, void *stream)
+{
+    if (!h || !src || !dst || !triplets_dev || !poses_dev || !ok_dev || n < 3 || T < 0) return TR_ERR_INVALID_ARG;
+    if (T == 0) return TR_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
+    const hipError_t e = launch_fit_triplets(src, dst, n, triplets_dev, T, poses_dev, ok_dev, h->num_cus * 4,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TR_OK : TR_ERR_HIP;
+}
+
 tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32_t n, const float *poses_dev,
                          int32_t P, float theta, int32_t metric, int32_t *in_dev, float *score_dev, void *stream)
 {

@@ -30,7 +30,7 @@ TR_NUM_STAGES = len(STAGES)
 EXPORTS = ("tr_create", "tr_destroy", "tr_register", "tr_register_batch", "tr_scorer_load",
            "tr_scorer_save", "tr_scorer_set", "tr_scorer_get", "tr_features_batch", "tr_mlp_forward",
            "tr_mlp_grads", "tr_train_step", "tr_debug_copy", "tr_stage_times", "tr_status_string",
-           "tr_tuning_get", "tr_tuning_set", "tr_autotune", "tr_score_poses")
+           "tr_tuning_get", "tr_tuning_set", "tr_autotune", "tr_score_poses", "tr_fit_triplets")
 
 
 class tr_params(ct.Structure):
@@ -79,6 +79,7 @@ def lib():
         L.tr_debug_copy.argtypes = [vp, I32, I32, vp, ct.c_size_t, ct.POINTER(ct.c_size_t)]
         L.tr_stage_times.argtypes = [vp, ct.POINTER(ct.c_float), I32]
         L.tr_score_poses.argtypes = [vp, vp, vp, I32, vp, I32, ct.c_float, I32, vp, vp, vp]
+        L.tr_fit_triplets.argtypes = [vp, vp, vp, I32, vp, I32, vp, vp, vp]
         L.tr_tuning_get.argtypes = [vp, I32, I32, ct.POINTER(tr_tuning)]
         L.tr_tuning_set.argtypes = [vp, I32, I32, ct.POINTER(tr_tuning)]
         L.tr_autotune.argtypes = [vp, vp, vp, vp, I32, I32, ct.POINTER(tr_params), vp, vp, vp,
@@ -152,6 +153,11 @@ def tr_register(h, src, dst, n, params, out, mask=None):
 def tr_register_batch(h, src, dst, offsets, B, max_n, params, out, masks=None):
     _ck(lib().tr_register_batch(h, _ptr(src), _ptr(dst), _ptr(offsets), int(B), int(max_n), ct.byref(params),
                                 _ptr(out), _ptr(masks), _stream()), "tr_register_batch")
+
+
+def tr_fit_triplets(h, src, dst, n, triplets, T_, poses_out, ok_out):
+    _ck(lib().tr_fit_triplets(h, _ptr(src), _ptr(dst), int(n), _ptr(triplets), int(T_), _ptr(poses_out),
+                              _ptr(ok_out), _stream()), "tr_fit_triplets")
 
 
 def tr_score_poses(h, src, dst, n, poses, P, theta, metric, in_out, score_out=None):

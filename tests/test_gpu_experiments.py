@@ -1,0 +1,65 @@
+"""GPU: the triplet-fit entry point against the oracle's fits, and the synthetic
+ablation reruns (correct-hypothesis counts, tau/K1/K2 sweeps, 3- vs 10-clique
+discrepancy) on small inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_01439_amd import synth
+from paper_2507_01439_amd import turboreg as T
+from parity import POSE_M, POSE_RAD, rot_angle, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def reg():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    r = T.Registrar(max_n=2000, max_batch=1, max_k1=500, max_k2=8)
+    yield r
+    r.close()
+
+
+def test_fit_triplets_matches_oracle(reg):
+    p = synth.make_pair(synth.CONFIGS["indoor_n1000"], synth.pair_seed(11, 0))
+    rng = np.random.default_rng(5)
+    tri = rng.integers(0, 1000, (600, 3)).astype(np.int32)
+    tri[:5] = [[1, 1, 2], [3, 3, 3], [-1, 2, 3], [0, 1, 1000], [7, 8, 9]]   # repeats, out of range
+    poses = torch.empty((600, 12), dtype=torch.float32, device="cuda")
+    ok = torch.empty(600, dtype=torch.int32, device="cuda")
+    T.tr_fit_triplets(reg.h, to_dev(torch, p.src), to_dev(torch, p.dst), 1000, to_dev(torch, tri), 600, poses, ok)
+    torch.cuda.synchronize()
+    poses, ok = poses.cpu().numpy(), ok.cpu().numpy()
+    assert ok[2] == 0 and ok[3] == 0
+    ident = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], np.float32)
+    assert np.array_equal(poses[2], ident) and np.array_equal(poses[3], ident)
+    inr = (tri >= 0).all(1) & (tri < 1000).all(1)
+    R64, t64, fl = oracle.kabsch(p.src, p.dst, np.where(inr[:, None], tri, -1))
+    worst_r = worst_t = 0.0
+    for k in np.nonzero(fl == 1)[0]:   # well-conditioned triplets: the same fit within the pose bar
+        assert ok[k] == 1
+        worst_r = max(worst_r, rot_angle(poses[k, :9].reshape(3, 3), R64[k]))
+        worst_t = max(worst_t, float(np.abs(poses[k, 9:].astype(np.float64) - t64[k]).max()))
+    say(worst_r, worst_t)
+    assert worst_r <= POSE_RAD and worst_t <= POSE_M
+    dposes = torch.empty((600, 12), dtype=torch.float32, device="cuda")
+    dok = torch.empty(600, dtype=torch.int32, device="cuda")
+    with pytest.raises(T.TurboRegError):   # n < 3
+        T.tr_fit_triplets(reg.h, to_dev(torch, p.src), to_dev(torch, p.dst), 2, to_dev(torch, tri), 600, dposes, dok)
+
+
+def test_experiments_small(reg):
+    from paper_2507_01439_amd import experiments
+    base = synth.CONFIGS["indoor_n1000"].replace(inlier_ratio=0.05)
+    pairs = [synth.make_pair(base, synth.pair_seed(11, 10 + b)) for b in range(2)]
+    ch = experiments.correct_hypotheses(reg, torch, pairs, hs=(100, 400))
+    say(ch)
+    assert ch[400]["successful_poses"] >= ch[100]["successful_poses"] >= 0
+    sw = experiments.sweep(reg, torch, pairs, taus=(0.05, 0.1), k1s=(100, 200), k2s=(1, 3), k10=200)
+    say(sw)
+    assert all(0 <= v["success_rate"] <= 1 for part in sw.values() for v in part.values())
+    cd = experiments.clique_discrepancy(reg, torch, taus=(0.02, 0.2), n=800, cliques=3)
+    say(cd)
+    assert cd[0.02]["cliques"] > 0 and cd[0.02]["fits"] > 0
