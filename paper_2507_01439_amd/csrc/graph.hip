@@ -295,29 +295,52 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         }
         uint32_t rowbits[4] = {0, 0, 0, 0}, colbits[4] = {0, 0, 0, 0};
         int nbnd = 0, nedge = 0;
+        // every pair of an interior tile (bi < bj, both blocks below n) is live with i < j: the
+        // edges are the bits set, and a boundary pair (|delta - tau| < 1e-6) can only occur in a
+        // lane that took the exact path (the guard band is wider)
+        const bool interior = !LEARNED && bi < bj && (bj + 1) * kCompatTile <= d.n;
+        if (interior) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            const int r = ty * 4 + a, i = bi * kCompatTile + r;
+            for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int c = tx * 4 + e, j = bj * kCompatTile + c;
-                const bool live = i != j && i < d.n && j < d.n;
-                const uint32_t bit = (live && dl[a][e] <= tau) ? 1u : 0u;
-                rowbits[a] |= bit << (8 * e);
-                colbits[e] |= bit << (8 * a);
-                if (live && i < j) {
-                    nbnd += __builtin_fabsf(dl[a][e] - tau) < 1e-6f;
-                    nedge += (int)bit;
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t bit = dl[a][e] <= tau ? 1u : 0u;
+                    rowbits[a] |= bit << (8 * e);
+                    colbits[e] |= bit << (8 * a);
                 }
-                if (LEARNED && live) {
-                    int bin = 0;
+            nedge = __builtin_popcount(rowbits[0]) + __builtin_popcount(rowbits[1]) + __builtin_popcount(rowbits[2]) +
+                    __builtin_popcount(rowbits[3]);
+            if (need_exact) {
 #pragma unroll
-                    for (int k = 1; k < 16; ++k) bin += dl[a][e] >= (float)k * q;
-                    atomicAdd(&hrow[r][bin], 1);
-                    atomicAdd(&hrow[r][16], (int)bit);
-                    if (!diag) {
-                        atomicAdd(&hcol[c][bin], 1);
-                        atomicAdd(&hcol[c][16], (int)bit);
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) nbnd += __builtin_fabsf(dl[a][e] - tau) < 1e-6f;
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int r = ty * 4 + a, i = bi * kCompatTile + r;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = tx * 4 + e, j = bj * kCompatTile + c;
+                    const bool live = i != j && i < d.n && j < d.n;
+                    const uint32_t bit = (live && dl[a][e] <= tau) ? 1u : 0u;
+                    rowbits[a] |= bit << (8 * e);
+                    colbits[e] |= bit << (8 * a);
+                    if (live && i < j) {
+                        nbnd += __builtin_fabsf(dl[a][e] - tau) < 1e-6f;
+                        nedge += (int)bit;
+                    }
+                    if (LEARNED && live) {
+                        int bin = 0;
+#pragma unroll
+                        for (int k = 1; k < 16; ++k) bin += dl[a][e] >= (float)k * q;
+                        atomicAdd(&hrow[r][bin], 1);
+                        atomicAdd(&hrow[r][16], (int)bit);
+                        if (!diag) {
+                            atomicAdd(&hcol[c][bin], 1);
+                            atomicAdd(&hcol[c][16], (int)bit);
+                        }
                     }
                 }
             }
