@@ -297,7 +297,6 @@ def main():
             T.tr_scorer_load(lreg.h, f.read())
         line["learned_vs_plain"] = eval_learned.compare(lreg, torch, pairs, k1_sweep=sweep, ref_k1=ref)
         lreg.close()
-        lreg.close()
     if args.cpu_budget > 0 and args.workload in ("indoor_n5000", "indoor_n1000"):
         line["cpu_baseline"] = cpu_baseline([g[0] for g in groups], cfg, args.cpu_budget)
     reg.close()
