@@ -15,6 +15,11 @@ constexpr int kPrepRows = 256;    // rows per work item of the prep / feature ke
 constexpr int kRankSortMax = 4096; // candidate lists up to this size are ordered by a rank sort
 constexpr int kScoreHyp = 64;     // hypotheses per scoring work item (four per thread)
 constexpr int kScorePts = 256;    // points per scoring work item (staged in LDS)
+// Counters that many workgroups update with device-scope atomics are spread out: same-address
+// device atomics are served one after another, so one shared counter serialises the stage.
+constexpr int kCollectRegions = 8; // pivot collection: one pool region and counter per XCD
+constexpr int kHypGroup = 16;     // clique-search items per first-level ticket
+constexpr int kTickLine = 32;     // int32 per counter: one counter per 128-byte line
 
 // Work-list stages whose per-pair item counts depend on N_b; each has a
 // prefix array of B+1 entries in Plan::pre.
@@ -41,10 +46,7 @@ struct PairState {
     int32_t fallback;   // learned scores were not finite
     int32_t fast;       // every pair of weight >= alpha fits the pivot pool: collected unordered, then sorted
     int32_t ncand;      // keys the sort ranks (fast: c_gt + all ties; else K)
-    int32_t cand_cnt;   // keys collected so far (fast path)
-    int32_t done;       // workgroups of a fused stage that have finished this pair
-    int32_t n_valid;    // hypotheses with a clique
-    uint64_t best;      // max over hypotheses of (IN + 1) << 32 | (2^32 - 1 - h); 0: none
+    int32_t done;       // ticket groups of the clique-search stage that have finished this pair
 };
 
 struct Plan {
@@ -78,7 +80,13 @@ struct Work {
                               // from its first column j > i) holds a pair of weight >= alpha
     int32_t *blkcnt;          // max_batch x nblk x 2
     int32_t nblk_stride;      // blocks of kRowsPerItem rows per pair (for max_n)
-    uint64_t *cand;           // max_batch x pool_cap selection candidates (sort keys)
+    uint64_t *cand;           // max_batch x kCollectRegions x pool_cap selection candidates (sort keys); the
+                              // ordered path writes region 0 only
+    int32_t *tick;            // max_batch x tick_stride counters, kTickLine apart: kCollectRegions collection
+                              // counters, then one ticket per group of kHypGroup clique-search items
+    int32_t tick_stride;
+    uint64_t *hyp_rec;        // max_batch x rec_stride: per clique-search item, its best key and valid count
+    int32_t rec_stride;       // 2 x the most clique-search items of a pair (k1_cap / 4, rounded up)
     int32_t pool_cap;
     int32_t *pivots_plain;    // max_batch x pool_cap x 3
     int32_t *pivots;          // pivots the clique search uses: max_batch x piv_stride x 3

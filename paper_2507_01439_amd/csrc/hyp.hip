@@ -358,17 +358,61 @@ __device__ __forceinline__ int row16_scan(int v)
     return v;
 }
 
+// Sum over the 64 lanes (DPP), returned to every lane.
+__device__ __forceinline__ int wave_total(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // The pair's result once every hypothesis is scored: argmax of IN (lowest h
 // on ties), the compatibility counts summed over the pair's tiles, the result
 // record and the inlier mask under the selected pose. Run by one 256-thread
-// workgroup.
-__device__ void select_pair(const Work &w, int b)
+// workgroup (every thread calls it).
+__device__ void select_pair(const Work &w, int b, int ipp)
 {
-    const int tid = threadIdx.x;
+    __shared__ uint64_t red_k[4];
+    __shared__ int32_t red_n[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const PairDesc d = pair_desc(w, b);
-    // the argmax and the counts were folded into the pair's state by atomics of this launch
-    const uint64_t best = __hip_atomic_load(&w.state[b].best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int nvalid = __hip_atomic_load(&w.state[b].n_valid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // every work item of the pair left its best key and valid count in its record (device scope,
+    // written by other workgroups of this launch); four records per thread are loaded at once
+    const uint64_t *rec = w.hyp_rec + (int64_t)b * w.rec_stride;
+    uint64_t best = 0;
+    int nvalid = 0;
+    for (int k0 = tid; k0 < ipp; k0 += 1024) {
+        uint64_t rk[4], rn[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 256 * u;
+            rk[u] = k < ipp ? __hip_atomic_load(rec + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+            rn[u] = k < ipp ? __hip_atomic_load(rec + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            best = rk[u] > best ? rk[u] : best;
+            nvalid += (int)rn[u];
+        }
+    }
+    best = wave_max_u64(best);
+    nvalid = wave_total(nvalid);
+    if (lane == 0) {
+        red_k[wv] = best;
+        red_n[wv] = nvalid;
+    }
+    __syncthreads();
+    best = red_k[0];
+    nvalid = red_n[0];
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+        best = red_k[k] > best ? red_k[k] : best;
+        nvalid += red_n[k];
+    }
     const PairState st = w.state[b];
     const int nbnd = st.n_boundary, nedge = st.n_edges, nbad = st.nonfinite;
     const int hbest = best ? (int)(0xFFFFFFFFu - (uint32_t)best) : -1;
@@ -432,7 +476,7 @@ __device__ void select_pair(const Work &w, int b)
     }
 }
 
-// Sum over the 64 lanes (DPP), valid in every lane.
+// One DPP move of a float (the control word is a template constant).
 template <int CTRL, int RMASK>
 __device__ __forceinline__ float dpp_f(float x)
 {
@@ -451,17 +495,6 @@ __device__ __forceinline__ float wave_total_f(float v)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-__device__ __forceinline__ int wave_total(int v)
-{
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
 __device__ __forceinline__ void store_agent(float *p, float v)
 {
     __hip_atomic_store(reinterpret_cast<uint32_t *>(p), __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -474,16 +507,18 @@ __device__ __forceinline__ void store_agent(float *p, float v)
 // thread reading its matches from L2 (two per step, four steps of loads in
 // flight) and evaluating eight poses held in registers per pass; wave sums
 // (DPP) are added into per-hypothesis LDS totals, so IN needs no global
-// atomics. IN and the poses are stored at device scope and each item folds
-// its best (IN, h) and valid count into the pair's state; the workgroup that
-// finishes a pair's last item (atomic ticket, no waiting) selects the result.
+// atomics. IN and the poses are stored at device scope, each item stores its
+// best (IN, h) and valid count in its own record, and the workgroup that
+// finishes a pair's last item (two levels of atomic tickets, no waiting)
+// selects the result.
 template <int KMAX, int METRIC>
 __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
 {
     __shared__ float pose_l[16 * TR_MAX_K2][12];
     __shared__ int32_t valid_l[16 * TR_MAX_K2], tot_l[16 * TR_MAX_K2];
     __shared__ float sc_l[4][16 * TR_MAX_K2];   // per-wave error-score sums (METRIC only)
-    __shared__ int32_t last;
+    __shared__ uint64_t key_l[4];
+    __shared__ int32_t nv_l[4], last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ipp = (w.k1 + ppw - 1) / ppw, total = B * ipp;
     const float th2 = w.theta * w.theta;
@@ -589,20 +624,42 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                 }
             }
         }
-        // this item's best hypothesis and valid count, folded into the pair's state (lowest h on ties)
+        // this item's best hypothesis (lowest h on ties) and valid count, stored in its own record
         key = wave_max_u64(key);
         nv = wave_total(nv);
-        if (lane == 0 && wv < (nloc + 63) / 64) {
-            if (key) atomicMax(reinterpret_cast<unsigned long long *>(&w.state[b].best), (unsigned long long)key);
-            if (nv) atomicAdd(&w.state[b].n_valid, nv);
+        if (lane == 0) {
+            key_l[wv] = key;
+            nv_l[wv] = nv;
         }
-        // every store and atomic of this item has been acknowledged before the ticket; the last
-        // workgroup of the pair reads the state and the best pose with device-scope loads
+        __syncthreads();
+        if (tid == 0) {
+            uint64_t k = key_l[0];
+            int n = nv_l[0];
+#pragma unroll
+            for (int v = 1; v < 4; ++v) {
+                k = key_l[v] > k ? key_l[v] : k;
+                n += nv_l[v];
+            }
+            uint64_t *rec = w.hyp_rec + (int64_t)b * w.rec_stride + 2 * g;
+            __hip_atomic_store(rec, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(rec + 1, (uint64_t)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // every store of this item has been acknowledged before its ticket. Two levels of tickets:
+        // the last item of a group of kHypGroup takes a ticket of the pair, and the workgroup
+        // that takes the pair's last ticket reads the records and the best pose with device-scope
+        // loads (no counter is shared by more than kHypGroup items or ceil(ipp / kHypGroup) groups)
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (tid == 0) last = atomicAdd(&w.state[b].done, 1) == ipp - 1;
+        if (tid == 0) {
+            const int grp = g / kHypGroup, ngrp = (ipp + kHypGroup - 1) / kHypGroup;
+            const int gsz = min(kHypGroup, ipp - grp * kHypGroup);
+            int32_t *gt = w.tick + (int64_t)b * w.tick_stride + (kCollectRegions + grp) * kTickLine;
+            bool l = atomicAdd(gt, 1) == gsz - 1;
+            if (l) l = atomicAdd(&w.state[b].done, 1) == ngrp - 1;
+            last = l;
+        }
         __syncthreads();
-        if (last) select_pair(w, b);
+        if (last) select_pair(w, b, ipp);
         __syncthreads();   // LDS is the next item's
     }
 }

@@ -140,6 +140,9 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     const int b = blockIdx.x;
     const PairDesc d = pair_desc(w, b);
     const int64_t K = d.kpiv;
+    // this call's counters of the pair (collection regions, clique-search tickets) start at zero;
+    // the later kernels of the call update them
+    for (int k = threadIdx.x; k < w.tick_stride / kTickLine; k += 1024) w.tick[(int64_t)b * w.tick_stride + k * kTickLine] = 0;
     if (K <= 0) return;
     const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.hist_stride;
     // four consecutive bins per thread: one 16-byte load from each of the 16 copies, all issued
@@ -231,7 +234,9 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
         const bool live = i < d.n && !(alpha > 0 && rm < alpha);
         const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
         const int c_lo = (i + 1) >> 3;
-        uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
+        // the pool region and counter of this workgroup's XCD (workgroup g runs on XCD g mod 8)
+        const int rgn = blockIdx.x & (kCollectRegions - 1);
+        uint64_t *cand = w.cand + ((int64_t)b * kCollectRegions + rgn) * w.pool_cap;
         // mode 0: count (ordered path); 1: stage into buf; 2: write cand[base + ...]
         auto scan = [&](int mode, int &cnt, uint64_t &segs) {
             cnt = 0;
@@ -292,7 +297,7 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
             const int n_wg = nbuf;
             __syncthreads();   // every thread has read nbuf before it is reset
             if (n_wg == 0) continue;
-            if (tid == 0) base = atomicAdd(&w.state[b].cand_cnt, n_wg);
+            if (tid == 0) base = atomicAdd(&w.tick[(int64_t)b * w.tick_stride + rgn * kTickLine], n_wg);
             __syncthreads();
             if (n_wg <= kCollectCap) {
                 for (int k = tid; k < n_wg; k += 256)
@@ -362,7 +367,7 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
             }
         }
         __syncthreads();
-        uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
+        uint64_t *cand = w.cand + (int64_t)b * kCollectRegions * w.pool_cap;   // region 0
         const int c1 = (d.n + 7) >> 3;
         for (int rr = 0; rr < kRowsPerItem / 4; ++rr) {
             const int lr = wv * (kRowsPerItem / 4) + rr, i = blk * kRowsPerItem + lr;
@@ -439,12 +444,42 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int NC = K > 0 ? min(w.state[b].ncand, w.pool_cap) : 0;   // keys ranked; the first K are kept
+    const PairState st = w.state[b];
+    // the keys sit in the kCollectRegions regions of the pool (fast path: the count of each is its
+    // counter) or in region 0 (ordered path: exactly K)
+    int rb[kCollectRegions + 1];
+    rb[0] = 0;
+    if (K > 0 && st.fast) {
+        int c[kCollectRegions];
+#pragma unroll
+        for (int r = 0; r < kCollectRegions; ++r) c[r] = w.tick[(int64_t)b * w.tick_stride + r * kTickLine];
+#pragma unroll
+        for (int r = 0; r < kCollectRegions; ++r) rb[r + 1] = rb[r] + min(max(c[r], 0), w.pool_cap);
+    } else {
+#pragma unroll
+        for (int r = 0; r < kCollectRegions; ++r) rb[r + 1] = K > 0 ? st.ncand : 0;
+    }
+    // keys ranked (the first K are kept)
+    const int NC = K > 0 ? min(min(st.ncand, rb[kCollectRegions]), w.pool_cap) : 0;
     int32_t *out = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
     if (g * 64 >= max(NC, w.pool)) return;
-    const uint64_t *cand = w.cand + (int64_t)b * w.pool_cap;
+    const uint64_t *cand = w.cand + (int64_t)b * kCollectRegions * w.pool_cap;
     const int K16 = (NC + 15) & ~15;   // padded with keys larger than any real one
-    for (int k = tid; k < K16; k += 256) keys[k] = k < NC ? cand[k] : ~0ull;
+    for (int k0 = tid; k0 < K16; k0 += 256 * 8) {   // eight keys per thread loaded before any is stored
+        uint64_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + 256 * u;
+            int r = 0, o = 0;   // the region holding key k and its first key (rb is non-decreasing)
+#pragma unroll
+            for (int q = 1; q < kCollectRegions; ++q)
+                if (k >= rb[q]) { r = q; o = rb[q]; }
+            v[u] = k < NC ? cand[(int64_t)r * w.pool_cap + (k - o)] : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + 256 * u < K16) keys[k0 + 256 * u] = v[u];
+    }
     if (g == 0) {   // the pair's first workgroup: boundary pairs, edges and non-finite input over its tiles
         const int t0 = stage_first(w, kCompat, b), t1 = t0 + stage_count(w, kCompat, b);
         int c[3] = {0, 0, 0};

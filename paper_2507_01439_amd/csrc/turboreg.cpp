@@ -46,7 +46,9 @@ struct tr_handle {
     uint8_t *C = nullptr;
     uint16_t *G = nullptr;
     int32_t *ghist = nullptr, *rowmax = nullptr, *cnt_part = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
-    uint64_t *cand = nullptr, *rowseg = nullptr;
+    uint64_t *cand = nullptr, *rowseg = nullptr, *hyp_rec = nullptr;
+    int32_t *tick = nullptr;
+    int32_t tick_stride = 0, rec_stride = 0;
     int32_t *pivots_plain = nullptr, *pivots = nullptr, *cliques = nullptr, *inl = nullptr;
     float *poses = nullptr, *gscore = nullptr;
     int32_t *rowstat = nullptr, *mark = nullptr;
@@ -164,6 +166,10 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.blkcnt = h->blkcnt;
     w.nblk_stride = h->nblk_stride;
     w.cand = h->cand;
+    w.tick = h->tick;
+    w.tick_stride = h->tick_stride;
+    w.hyp_rec = h->hyp_rec;
+    w.rec_stride = h->rec_stride;
     w.rowseg = h->rowseg;
     w.pool_cap = h->pool_cap;
     w.pivots_plain = h->pivots_plain;
@@ -354,6 +360,11 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     h->k1_cap = max_k1;
     h->h_cap = max_k1 * max_k2;
     h->nblk_stride = (max_n + kRowsPerItem - 1) / kRowsPerItem;
+    {
+        const int items = (max_k1 + 3) / 4;   // clique-search work items of a pair (at least 4 pivots each)
+        h->rec_stride = 2 * items;
+        h->tick_stride = (kCollectRegions + (items + kHypGroup - 1) / kHypGroup) * kTickLine;
+    }
     h->pre_stride = max_batch + 1;
     const size_t B = max_batch, nn = (size_t)h->npad_max * h->npad_max;
     hipError_t e = hipSuccess;
@@ -374,7 +385,9 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     }
     A(alloc(h, &h->rowcnt, B * max_n * 2));
     A(alloc(h, &h->blkcnt, B * h->nblk_stride * 2));
-    A(alloc(h, &h->cand, B * h->pool_cap));
+    A(alloc(h, &h->cand, B * kCollectRegions * h->pool_cap));
+    A(alloc(h, &h->tick, B * h->tick_stride));
+    A(alloc(h, &h->hyp_rec, B * h->rec_stride));
     A(alloc(h, &h->rowseg, B * max_n));
     A(alloc(h, &h->pivots_plain, B * h->pool_cap * 3));
     A(alloc(h, &h->pivots, B * h->k1_cap * 3));
