@@ -205,10 +205,20 @@ __device__ bool fit_pose(const Work &w, const PairDesc &d, int ia, int ib, int i
 
 // ---------------------------------------------------------------- Eqs. 5-8
 
-// Candidate key: larger S first, then smaller z. Zero means "empty".
-__device__ __forceinline__ uint64_t clique_key(uint32_t S, uint32_t z)
+// Candidate key of a third vertex z: larger T = G(i,z) + G(j,z) first, then smaller z. The
+// clique weight S = G(i,j) + T (Eq. 7) differs from T by the same G(i,j) for every z of a pivot,
+// so T orders the candidates like S. Weights are below N <= 32767, so T < 2^16 and z < 2^15:
+// key = T * 2^15 + (32767 - z) fits 31 bits, and 0 means "empty" (a candidate has T >= 2).
+__device__ __forceinline__ uint32_t clique_key(uint32_t T, uint32_t z)
 {
-    return ((uint64_t)S << 32) | (uint64_t)(0xFFFFFFFFu - z);
+    return (T << 15) + (32767u - z);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
 }
 
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
@@ -222,26 +232,25 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
 }
 
 template <int KMAX>
-__device__ __forceinline__ void top_insert(uint64_t (&top)[KMAX], uint64_t k)
+__device__ __forceinline__ void top_insert(uint32_t (&top)[KMAX], uint32_t k)
 {
 #pragma unroll
     for (int s = 0; s < KMAX; ++s) {
-        const uint64_t t = top[s];
-        const bool gt = k > t;
-        top[s] = gt ? k : t;
-        k = gt ? t : k;
+        const uint32_t t = top[s];
+        top[s] = max(t, k);
+        k = min(t, k);
     }
 }
 
 // One wavefront per pivot (p of pair b). On the O2Graph each lane reads eight consecutive
 // weights of rows i and j with one 16-byte load each (the wave covers 512
-// third vertices per step, z > j only); on the undirected graph lanes stride
-// over z and read the lower triangle through the transpose. Each lane keeps
-// its KMAX best keys sorted in registers (compare-and-swap insertion, no
-// dynamic register indexing); K2 rounds of a wave-wide max then pick the
-// pivot's cliques in (S desc, z asc) order and writes them (slot-major);
-// lane s < K2 returns the third vertex of clique s (-1: none), pi / pj the
-// pivot (-1 for an empty slot).
+// third vertices per step, z > j only, and only the steps the row holds); on
+// the undirected graph lanes stride over z and read the lower triangle through
+// the transpose. Each lane keeps its KMAX best keys sorted in registers
+// (max / min insertion, no dynamic register indexing); K2 rounds of a
+// wave-wide max then pick the pivot's cliques in (S desc, z asc) order and
+// write them (slot-major); lane s < K2 returns the third vertex of clique s
+// (-1: none), pi / pj the pivot (-1 for an empty slot).
 template <int KMAX>
 __device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, int lane, int &pi, int &pj)
 {
@@ -250,7 +259,7 @@ __device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, int
         int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
         if (i < 0 || j < 0 || i >= d.n || j >= d.n || i == j) i = j = -1;   // an empty slot (or a bad index) finds no clique
         int32_t *cl = w.cliques + (int64_t)b * w.h_cap * 3;
-        uint64_t top[KMAX];
+        uint32_t top[KMAX];
 #pragma unroll
         for (int s = 0; s < KMAX; ++s) top[s] = 0;
         if (i >= 0) {
@@ -271,18 +280,28 @@ __device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, int
                         qj[u] = c < c1 ? *reinterpret_cast<const uint4 *>(rj + 8 * c) : make_uint4(0, 0, 0, 0);
                     }
                     if (wij == 0) continue;   // not an edge: no clique (Eq. 8)
+                    const int steps = min(16, (c1 - c0 + 63) >> 6);   // the same on every lane
 #pragma unroll
                     for (int u = 0; u < 16; ++u) {
+                        if (u >= steps) continue;   // uniform: the loop stays unrolled
                         const int c = c0 + 64 * u + lane;
+                        // elements e of the chunk with j < 8c + e < n (none when c >= c1)
+                        const int lo = min(max(j + 1 - 8 * c, 0), 8), hi = min(max(d.n - 8 * c, 0), 8);
+                        const uint32_t vm = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                        const uint32_t zb = 32767u - 8u * (uint32_t)c;
                         const uint32_t ui[4] = {qi[u].x, qi[u].y, qi[u].z, qi[u].w};
                         const uint32_t uj[4] = {qj[u].x, qj[u].y, qj[u].z, qj[u].w};
 #pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int z = 8 * c + e;
-                            const int giz = (int)((ui[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                            const int gjz = (int)((uj[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                            if (z > j && z < d.n && giz > 0 && gjz > 0)
-                                top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
+                        for (int k = 0; k < 4; ++k) {
+                            // two weights per word; G(i,z) of elements outside the range masked to 0
+                            const uint32_t mw = (((vm >> (2 * k)) & 1u) ? 0xFFFFu : 0u) |
+                                                (((vm >> (2 * k + 1)) & 1u) ? 0xFFFF0000u : 0u);
+                            const uint32_t a = ui[k] & mw, bj = uj[k];
+                            const uint32_t t0 = (a & 0xFFFFu) + (bj & 0xFFFFu), t1 = (a >> 16) + (bj >> 16);
+                            const bool e0 = (a & 0xFFFFu) != 0 && (bj & 0xFFFFu) != 0;
+                            const bool e1 = (a >> 16) != 0 && (bj >> 16) != 0;
+                            top_insert<KMAX>(top, e0 ? (t0 << 15) + (zb - 2 * k) : 0u);
+                            top_insert<KMAX>(top, e1 ? (t1 << 15) + (zb - 2 * k - 1) : 0u);
                         }
                     }
                 }
@@ -291,20 +310,19 @@ __device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, int
                     if (z == i || z == j) continue;
                     const int giz = i < z ? G[i * npad + z] : G[(int64_t)z * npad + i];
                     const int gjz = j < z ? G[(int64_t)j * npad + z] : G[(int64_t)z * npad + j];
-                    if (giz > 0 && gjz > 0)
-                        top_insert<KMAX>(top, clique_key((uint32_t)(wij + giz + gjz), (uint32_t)z));
+                    if (giz > 0 && gjz > 0) top_insert<KMAX>(top, clique_key((uint32_t)(giz + gjz), (uint32_t)z));
                 }
             }
         }
         int zmine = -1;   // lane s < K2 keeps the third vertex of clique s
         for (int s = 0; s < w.k2; ++s) {
-            const uint64_t best = wave_max_u64(top[0]);
+            const uint32_t best = wave_max_u32(top[0]);
             if (best != 0 && top[0] == best) {          // keys are unique per z: one owner
 #pragma unroll
                 for (int q = 0; q + 1 < KMAX; ++q) top[q] = top[q + 1];
                 top[KMAX - 1] = 0;
             }
-            const int z = best ? (int32_t)(0xFFFFFFFFu - (uint32_t)best) : -1;
+            const int z = best ? (int32_t)(32767u - (best & 0x7FFFu)) : -1;
             if (lane == s) zmine = z;
             if (lane == 0) {
                 const int64_t h = (int64_t)s * w.k1 + p;
