@@ -390,12 +390,14 @@ __device__ __forceinline__ int wave_total(int v)
 
 // The pair's result once every hypothesis is scored: argmax of IN (lowest h
 // on ties), the compatibility counts summed over the pair's tiles, the result
-// record and the inlier mask under the selected pose. Run by one 256-thread
-// workgroup (every thread calls it).
+// record and the inlier mask under the selected pose. Run by one workgroup of
+// NW waves (every thread calls it).
+template <int NW>
 __device__ void select_pair(const Work &w, int b, int ipp)
 {
-    __shared__ uint64_t red_k[4];
-    __shared__ int32_t red_n[4];
+    constexpr int NT = 64 * NW;
+    __shared__ uint64_t red_k[NW];
+    __shared__ int32_t red_n[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const PairDesc d = pair_desc(w, b);
     // every work item of the pair left its best key and valid count in its record (device scope,
@@ -403,11 +405,11 @@ __device__ void select_pair(const Work &w, int b, int ipp)
     const uint64_t *rec = w.hyp_rec + (int64_t)b * w.rec_stride;
     uint64_t best = 0;
     int nvalid = 0;
-    for (int k0 = tid; k0 < ipp; k0 += 1024) {
+    for (int k0 = tid; k0 < ipp; k0 += 4 * NT) {
         uint64_t rk[4], rn[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + 256 * u;
+            const int k = k0 + NT * u;
             rk[u] = k < ipp ? __hip_atomic_load(rec + 2 * k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
             rn[u] = k < ipp ? __hip_atomic_load(rec + 2 * k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
         }
@@ -427,7 +429,7 @@ __device__ void select_pair(const Work &w, int b, int ipp)
     best = red_k[0];
     nvalid = red_n[0];
 #pragma unroll
-    for (int k = 1; k < 4; ++k) {
+    for (int k = 1; k < NW; ++k) {
         best = red_k[k] > best ? red_k[k] : best;
         nvalid += red_n[k];
     }
@@ -470,11 +472,11 @@ __device__ void select_pair(const Work &w, int b, int ipp)
         // eight matches per thread: their loads are all issued before any residual is formed
         const float th2 = w.theta * w.theta;
         constexpr int kM = 8;
-        for (int k0 = tid; k0 < d.n; k0 += 256 * kM) {
+        for (int k0 = tid; k0 < d.n; k0 += NT * kM) {
             float x[kM][3], y[kM][3];
 #pragma unroll
             for (int m = 0; m < kM; ++m) {
-                const int64_t g = d.pt_off + min(k0 + 256 * m, d.n - 1);
+                const int64_t g = d.pt_off + min(k0 + NT * m, d.n - 1);
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
                     x[m][f] = w.src[3 * g + f];
@@ -483,7 +485,7 @@ __device__ void select_pair(const Work &w, int b, int ipp)
             }
 #pragma unroll
             for (int m = 0; m < kM; ++m) {
-                const int k = k0 + 256 * m;
+                const int k = k0 + NT * m;
                 if (k < d.n) {
                     const bool in = hbest >= 0 &&
                                     residual2(ps, x[m][0], x[m][1], x[m][2], y[m][0], y[m][1], y[m][2]) <= th2;
@@ -518,25 +520,28 @@ __device__ __forceinline__ void store_agent(float *p, float v)
     __hip_atomic_store(reinterpret_cast<uint32_t *>(p), __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Hypotheses of ppw pivots per work item (item = pair b, pivots g*ppw ..):
-// wave v finds the cliques of pivots v, v+4, ... (Eqs. 5-8) and lanes 0..K2-1
-// fit their poses (Section 3.5) into LDS; then the whole workgroup scores the
-// item's ppw*K2 hypotheses against all N matches of the pair (Eq. 9), each
-// thread reading its matches from L2 (two per step, four steps of loads in
-// flight) and evaluating eight poses held in registers per pass; wave sums
+// Hypotheses of ppw pivots per work item (item = pair b, pivots g*ppw ..), one
+// workgroup of NW waves: wave v finds the cliques of pivots v, v+NW, ...
+// (Eqs. 5-8) and lanes 0..K2-1 fit their poses (Section 3.5) into LDS; then
+// the whole workgroup scores the item's ppw*K2 hypotheses against all N
+// matches of the pair (Eq. 9), each thread reading four matches per step from
+// L2 (the next step's loads in flight) and evaluating eight poses held in
+// registers per pass; wave sums
 // (DPP) are added into per-hypothesis LDS totals, so IN needs no global
 // atomics. IN and the poses are stored at device scope, each item stores its
 // best (IN, h) and valid count in its own record, and the workgroup that
 // finishes a pair's last item (two levels of atomic tickets, no waiting)
 // selects the result.
-template <int KMAX, int METRIC>
-__global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
+template <int KMAX, int METRIC, int NW>
+__global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
 {
+    constexpr int NT = 64 * NW;
+    static_assert(METRIC == 0 || NW == 4, "error-score sums keep the four-wave order of k_score_poses");
     __shared__ float pose_l[16 * TR_MAX_K2][12];
     __shared__ int32_t valid_l[16 * TR_MAX_K2], tot_l[16 * TR_MAX_K2];
     __shared__ float sc_l[4][16 * TR_MAX_K2];   // per-wave error-score sums (METRIC only)
-    __shared__ uint64_t key_l[4];
-    __shared__ int32_t nv_l[4], last;
+    __shared__ uint64_t key_l[NW];
+    __shared__ int32_t nv_l[NW], last;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ipp = (w.k1 + ppw - 1) / ppw, total = B * ipp;
     const float th2 = w.theta * w.theta;
@@ -545,8 +550,9 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
         const PairDesc d = pair_desc(w, b);
         const int nloc = ppw * w.k2;   // local hypothesis hl = (pivot lp) * K2 + slot
         if (tid < 16 * TR_MAX_K2) tot_l[tid] = 0;
-        for (int r = 0; r < ppw / 4; ++r) {
-            const int lp = r * 4 + wv, p = g * ppw + lp;
+        for (int r = 0; r < (ppw + NW - 1) / NW; ++r) {
+            const int lp = r * NW + wv, p = g * ppw + lp;
+            if (lp >= ppw) break;   // the same on the whole wave
             int pi = -1, pj = -1, z = -1;
             if (p < w.k1) z = clique_search<KMAX>(w, d, b, p, lane, pi, pj);
             if (lane < w.k2) {
@@ -575,7 +581,7 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
             auto load4 = [&](int k0) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const int64_t gi = d.pt_off + min(k0 + 256 * m, d.n - 1);
+                    const int64_t gi = d.pt_off + min(k0 + NT * m, d.n - 1);
 #pragma unroll
                     for (int f = 0; f < 3; ++f) {
                         x[m][f] = w.src[3 * gi + f];
@@ -584,7 +590,7 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                 }
             };
             load4(tid);
-            for (int k0 = tid; k0 < d.n; k0 += 1024) {
+            for (int k0 = tid; k0 < d.n; k0 += 4 * NT) {
                 float cx[4][3], cy[4][3];
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
@@ -593,10 +599,10 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
                         cx[m][f] = x[m][f];
                         cy[m][f] = y[m][f];
                     }
-                if (k0 + 1024 < d.n) load4(k0 + 1024);
+                if (k0 + 4 * NT < d.n) load4(k0 + 4 * NT);
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const bool in = k0 + 256 * m < d.n;
+                    const bool in = k0 + NT * m < d.n;
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const float r2 = residual2(ps[u], cx[m][0], cx[m][1], cx[m][2], cy[m][0], cy[m][1], cy[m][2]);
@@ -654,7 +660,7 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
             uint64_t k = key_l[0];
             int n = nv_l[0];
 #pragma unroll
-            for (int v = 1; v < 4; ++v) {
+            for (int v = 1; v < NW; ++v) {
                 k = key_l[v] > k ? key_l[v] : k;
                 n += nv_l[v];
             }
@@ -677,7 +683,7 @@ __global__ void __launch_bounds__(256) k_hyp(Work w, int B, int ppw)
             last = l;
         }
         __syncthreads();
-        if (last) select_pair(w, b, ipp);
+        if (last) select_pair<NW>(w, b, ipp);
         __syncthreads();   // LDS is the next item's
     }
 }
@@ -802,15 +808,17 @@ hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s)
     const int total = B * ((w.k1 + ppw - 1) / ppw);
     grid = max(1, min(total, grid));
     const bool small = w.k2 <= 2;
+    // inlier-number ranking: eight waves per workgroup (two per SIMD) share the scoring; the
+    // error-based rankings keep four, the summation order tr_score_poses reproduces
     if (w.metric == 1) {
-        if (small) hipLaunchKernelGGL((k_hyp<2, 1>), dim3(grid), dim3(256), 0, s, w, B, ppw);
-        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 1>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        if (small) hipLaunchKernelGGL((k_hyp<2, 1, 4>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 1, 4>), dim3(grid), dim3(256), 0, s, w, B, ppw);
     } else if (w.metric == 2) {
-        if (small) hipLaunchKernelGGL((k_hyp<2, 2>), dim3(grid), dim3(256), 0, s, w, B, ppw);
-        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 2>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        if (small) hipLaunchKernelGGL((k_hyp<2, 2, 4>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 2, 4>), dim3(grid), dim3(256), 0, s, w, B, ppw);
     } else {
-        if (small) hipLaunchKernelGGL((k_hyp<2, 0>), dim3(grid), dim3(256), 0, s, w, B, ppw);
-        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 0>), dim3(grid), dim3(256), 0, s, w, B, ppw);
+        if (small) hipLaunchKernelGGL((k_hyp<2, 0, 8>), dim3(grid), dim3(512), 0, s, w, B, ppw);
+        else hipLaunchKernelGGL((k_hyp<TR_MAX_K2, 0, 8>), dim3(grid), dim3(512), 0, s, w, B, ppw);
     }
     return hipGetLastError();
 }
