@@ -68,7 +68,8 @@ __device__ __forceinline__ void adj_col(const double (&A)[4][4], double (&v)[4])
 // 2005; Liu, Agrafiotis & Theobald, J. Comput. Chem. 31, 2010): Newton's
 // iteration on the characteristic polynomial
 //   det(lambda I - K) = lambda^4 - tr(K^2)/2 lambda^2 - tr(K^3)/3 lambda + det K
-// from E0 = (sum |p_a|^2 + sum |q_a|^2)/2, an upper bound of the root. The
+// from E0 = (sum |p_a|^2 + sum |q_a|^2)/2, an upper bound of the root, until
+// the step falls below 1e-15 relative or stops being positive. The
 // eigenvector is the largest column of adj(K - lambda I). When that column
 // vanishes (a repeated top eigenvalue: collinear or coincident points) the
 // cyclic Jacobi method on K decides instead. float64 throughout, then R and t
@@ -134,8 +135,11 @@ __device__ bool fit_pose(const Work &w, const PairDesc &d, int ia, int ib, int i
             const double fp = 2.0 * lam * (2.0 * l2 + c2) + c1;
             if (!(fp > 0.0)) break;
             const double step = f / fp;
+            // from above the largest root the exact steps are positive and shrink: a step that is
+            // not positive is rounding noise at the root (it would only oscillate there)
+            if (!(step > 0.0)) break;
             lam -= step;
-            if (fabs(step) <= 1e-15 * fabs(lam)) break;
+            if (step <= 1e-15 * fabs(lam)) break;
         }
         // eigenvector: the largest column of adj(K - lambda I)
         double A[4][4];
@@ -400,6 +404,24 @@ __device__ void select_pair(const Work &w, int b, int ipp)
     __shared__ int32_t red_n[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const PairDesc d = pair_desc(w, b);
+    // the mask's first matches (kM per thread) do not depend on the selection: their loads are
+    // issued before the records are read
+    constexpr int kM = 12;
+    const bool want_mask = w.masks && d.n > 0;
+    float x[kM][3], y[kM][3];
+    auto load_pts = [&](int k0) {
+#pragma unroll
+        for (int m = 0; m < kM; ++m) {
+            const int64_t g = d.pt_off + min(k0 + NT * m, d.n - 1);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                x[m][f] = w.src[3 * g + f];
+                y[m][f] = w.dst[3 * g + f];
+            }
+        }
+    };
+    if (want_mask) load_pts(tid);
+    const PairState st = w.state[b];
     // every work item of the pair left its best key and valid count in its record (device scope,
     // written by other workgroups of this launch); four records per thread are loaded at once
     const uint64_t *rec = w.hyp_rec + (int64_t)b * w.rec_stride;
@@ -433,7 +455,6 @@ __device__ void select_pair(const Work &w, int b, int ipp)
         best = red_k[k] > best ? red_k[k] : best;
         nvalid += red_n[k];
     }
-    const PairState st = w.state[b];
     const int nbnd = st.n_boundary, nedge = st.n_edges, nbad = st.nonfinite;
     const int hbest = best ? (int)(0xFFFFFFFFu - (uint32_t)best) : -1;
     float ps[12];
@@ -468,21 +489,11 @@ __device__ void select_pair(const Work &w, int b, int ipp)
         r.reserved = 0;
         w.out[b] = r;
     }
-    if (w.masks && d.n > 0) {
-        // eight matches per thread: their loads are all issued before any residual is formed
+    if (want_mask) {
+        // kM matches per thread per step, their loads all issued before any residual is formed
         const float th2 = w.theta * w.theta;
-        constexpr int kM = 8;
         for (int k0 = tid; k0 < d.n; k0 += NT * kM) {
-            float x[kM][3], y[kM][3];
-#pragma unroll
-            for (int m = 0; m < kM; ++m) {
-                const int64_t g = d.pt_off + min(k0 + NT * m, d.n - 1);
-#pragma unroll
-                for (int f = 0; f < 3; ++f) {
-                    x[m][f] = w.src[3 * g + f];
-                    y[m][f] = w.dst[3 * g + f];
-                }
-            }
+            if (k0 != tid) load_pts(k0);
 #pragma unroll
             for (int m = 0; m < kM; ++m) {
                 const int k = k0 + NT * m;
