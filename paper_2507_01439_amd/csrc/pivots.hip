@@ -248,8 +248,10 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
                     const int c = c0 + 64 * u + lane;
                     q[u] = c < c1 ? *reinterpret_cast<const uint4 *>(row + 8 * c) : make_uint4(0, 0, 0, 0);
                 }
+                const int steps = min(16, (c1 - c0 + 63) >> 6);   // the same on every lane
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
+                    if (u >= steps) continue;   // uniform: the loop stays unrolled
                     const int c = c0 + 64 * u + lane;
                     if (mode == 0) {
                         bool hit = false;
@@ -257,28 +259,32 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
                         if (__any(hit)) segs |= 1ull << ((c0 - c_lo) / 64 + u);   // at most 64 segments (N < 32768)
                         continue;
                     }
+                    // bit e: pair (i, 8c + e) lies in i < j < n and weighs at least alpha
+                    const int lo = min(max(i + 1 - 8 * c, 0), 8), hi = min(max(d.n - 8 * c, 0), 8);
                     const uint32_t uw[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-                    int m = 0;
+                    uint32_t hits = 0;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int j = 8 * c + e, v = (int)((uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                        m += (c < c1 && j > i && j < d.n && v >= alpha);
-                    }
+                    for (int k = 0; k < 4; ++k)
+                        hits |= ((uint32_t)((int)(uw[k] & 0xFFFFu) >= alpha) << (2 * k)) |
+                                ((uint32_t)((int)(uw[k] >> 16) >= alpha) << (2 * k + 1));
+                    hits &= ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                    if (!__any(hits != 0)) continue;   // most chunks hold no key
+                    const int m = __builtin_popcount(hits);
                     const int incl = wave_incl_scan(m);
                     const int tot = __builtin_amdgcn_readlane(incl, 63);
-                    if (tot == 0) continue;
                     int off = 0;
                     if (lane == 63) off = atomicAdd(&nbuf, tot);
                     off = __builtin_amdgcn_readlane(off, 63) + incl - m;
-                    if (m) {
+                    if (hits) {
 #pragma unroll
                         for (int e = 0; e < 8; ++e) {
-                            const int j = 8 * c + e, v = (int)((uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                            if (j > i && j < d.n && v >= alpha) {
+                            if ((hits >> e) & 1u) {
+                                const uint32_t v = (uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                                const uint64_t key = pivot_key(v, i, 8 * c + e);
                                 if (mode == 2) {
-                                    if (base + off < w.pool_cap) cand[base + off] = pivot_key(v, i, j);
+                                    if (base + off < w.pool_cap) cand[base + off] = key;
                                 } else if (off < kCollectCap) {
-                                    buf[off] = pivot_key(v, i, j);
+                                    buf[off] = key;
                                 }
                                 ++off;
                             }
