@@ -439,26 +439,31 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
 
 // Order the K keys of one pair by (w desc, i asc, j asc) and write (i, j, w).
 // Keys are distinct, so a key's rank is the number of smaller keys. Each
-// 256-thread workgroup copies the pair's K keys into its LDS and ranks 64 of
-// them: wave v counts the smaller keys in its quarter of the list with eight
-// 16-byte broadcast reads in flight, and the four partial counts are summed.
-// The work of one pair is spread over ceil(K/64) CUs.
-__global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
+// workgroup of kSortWaves waves copies the pair's K keys into its LDS and
+// ranks 64 of them: wave v counts the smaller keys in its slice of the list
+// with eight 16-byte broadcast reads in flight, and the partial counts are
+// summed. The work of one pair is spread over ceil(K/64) CUs.
+constexpr int kSortWaves = 16;
+constexpr int kSortThreads = 64 * kSortWaves;
+
+__global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pair)
 {
     extern __shared__ uint64_t keys[];
-    __shared__ int32_t part[4][64];
+    __shared__ int32_t part[kSortWaves][64];
+    __shared__ int32_t tally[kSortWaves][3];
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // the collection counters are read together with the state (they are zeroed for every pair)
+    int c[kCollectRegions];
+#pragma unroll
+    for (int r = 0; r < kCollectRegions; ++r) c[r] = w.tick[(int64_t)b * w.tick_stride + r * kTickLine];
     const PairState st = w.state[b];
     // the keys sit in the kCollectRegions regions of the pool (fast path: the count of each is its
     // counter) or in region 0 (ordered path: exactly K)
     int rb[kCollectRegions + 1];
     rb[0] = 0;
     if (K > 0 && st.fast) {
-        int c[kCollectRegions];
-#pragma unroll
-        for (int r = 0; r < kCollectRegions; ++r) c[r] = w.tick[(int64_t)b * w.tick_stride + r * kTickLine];
 #pragma unroll
         for (int r = 0; r < kCollectRegions; ++r) rb[r + 1] = rb[r] + min(max(c[r], 0), w.pool_cap);
     } else {
@@ -471,11 +476,11 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     if (g * 64 >= max(NC, w.pool)) return;
     const uint64_t *cand = w.cand + (int64_t)b * kCollectRegions * w.pool_cap;
     const int K16 = (NC + 15) & ~15;   // padded with keys larger than any real one
-    for (int k0 = tid; k0 < K16; k0 += 256 * 8) {   // eight keys per thread loaded before any is stored
+    for (int k0 = tid; k0 < K16; k0 += kSortThreads * 8) {   // eight keys per thread loaded before any is stored
         uint64_t v[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const int k = k0 + 256 * u;
+            const int k = k0 + kSortThreads * u;
             int r = 0, o = 0;   // the region holding key k and its first key (rb is non-decreasing)
 #pragma unroll
             for (int q = 1; q < kCollectRegions; ++q)
@@ -484,16 +489,16 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (k0 + 256 * u < K16) keys[k0 + 256 * u] = v[u];
+            if (k0 + kSortThreads * u < K16) keys[k0 + kSortThreads * u] = v[u];
     }
     if (g == 0) {   // the pair's first workgroup: boundary pairs, edges and non-finite input over its tiles
         const int t0 = stage_first(w, kCompat, b), t1 = t0 + stage_count(w, kCompat, b);
         int c[3] = {0, 0, 0};
-        for (int tb = t0 + tid; tb < t1; tb += 256 * 8) {   // eight tiles per thread loaded before any is added
+        for (int tb = t0 + tid; tb < t1; tb += kSortThreads * 8) {   // eight tiles per thread loaded before any is added
             int v[8][3];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int t = tb + 256 * u;
+                const int t = tb + kSortThreads * u;
 #pragma unroll
                 for (int f = 0; f < 3; ++f) v[u][f] = t < t1 ? w.cnt_part[3 * (int64_t)t + f] : 0;
             }
@@ -508,15 +513,23 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
             for (int o = 32; o > 0; o >>= 1) c[f] += __shfl_xor(c[f], o, 64);
         }
         if (lane == 0) {
-            atomicAdd(&w.state[b].n_boundary, c[0]);
-            atomicAdd(&w.state[b].n_edges, c[1]);
-            if (c[2]) atomicOr(&w.state[b].nonfinite, 1);
+            tally[wv][0] = c[0];
+            tally[wv][1] = c[1];
+            tally[wv][2] = c[2];
+        }
+        __syncthreads();
+        if (tid < 3) {
+            int t = 0;
+            for (int v = 0; v < kSortWaves; ++v) t += tally[v][tid];
+            if (tid == 0) atomicAdd(&w.state[b].n_boundary, t);
+            else if (tid == 1) atomicAdd(&w.state[b].n_edges, t);
+            else if (t) atomicOr(&w.state[b].nonfinite, 1);
         }
     }
     __syncthreads();
     const int p = g * 64 + lane;
     const uint64_t mine = p < NC ? keys[p] : 0;
-    const int per = ((K16 / 16 + 3) / 4) * 16;
+    const int per = ((K16 / 16 + kSortWaves - 1) / kSortWaves) * 16;   // a slice of whole 16-key groups
     const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
     int r = 0;
     for (int q = q0; q < q1; q += 16) {
@@ -532,7 +545,9 @@ __global__ void __launch_bounds__(256) k_sort(Work w, int blocks_per_pair)
     part[wv][lane] = r;
     __syncthreads();
     if (wv != 0) return;
-    const int rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    int rk = 0;
+#pragma unroll
+    for (int v = 0; v < kSortWaves; ++v) rk += part[v][lane];
     if (p < NC && rk < K) {
         out[3 * rk] = (int32_t)((mine >> 20) & 0xFFFFF);
         out[3 * rk + 1] = (int32_t)(mine & 0xFFFFF);
@@ -553,8 +568,8 @@ hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s)
     hipLaunchKernelGGL(k_rowscan, dim3(grid_rows), dim3(256), 0, s, w);
     hipLaunchKernelGGL(k_emit, dim3(grid_rows), dim3(256), 0, s, w);
     const int bpp = (w.pool_cap + 63) / 64;   // the fast path may rank up to pool_cap keys
-    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(256), (size_t)((w.pool_cap + 15) & ~15) * sizeof(uint64_t), s, w,
-                       bpp);
+    hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(kSortThreads), (size_t)((w.pool_cap + 15) & ~15) * sizeof(uint64_t),
+                       s, w, bpp);
     return hipGetLastError();
 }
 
