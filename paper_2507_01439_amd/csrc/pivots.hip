@@ -9,7 +9,8 @@
 //   (the SC2 epilogue leaves kHistGroups weight histograms per pair and the
 //   per-row maximum of the upper triangle)
 //   k_thresh   sums the histograms; finds alpha, the pairs heavier than it
-//              (c_gt) and the ties to take (m)
+//              (c_gt) and the ties to take (m); sums the compatibility
+//              kernel's per-tile counts (boundary pairs, edges, non-finite)
 //   k_rowscan  fast path: collects every pair of weight >= alpha (when they
 //              fit the pool) for the sort; ordered path: per row, pairs
 //              > alpha and == alpha; per row block, their sums
@@ -137,6 +138,7 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     extern __shared__ int32_t hs[];
     __shared__ int64_t lds[17];
     __shared__ int32_t res[3];
+    __shared__ int32_t tally[16][3];
     const int b = blockIdx.x;
     const PairDesc d = pair_desc(w, b);
     const int64_t K = d.kpiv;
@@ -144,6 +146,21 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     // the later kernels of the call update them
     for (int k = threadIdx.x; k < w.tick_stride / kTickLine; k += 1024) w.tick[(int64_t)b * w.tick_stride + k * kTickLine] = 0;
     if (K <= 0) return;
+    // boundary pairs, edges and non-finite input of the pair, summed over its compatibility tiles;
+    // the first eight tiles per thread are loaded together with the histogram
+    constexpr int kTiles = 8;
+    const int t0 = stage_first(w, kCompat, b), t1 = t0 + stage_count(w, kCompat, b);
+    int cc[3] = {0, 0, 0};
+    int tv[kTiles][3];
+    auto load_tiles = [&](int tb) {
+#pragma unroll
+        for (int u = 0; u < kTiles; ++u) {
+            const int t = tb + 1024 * u;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) tv[u][f] = t < t1 ? w.cnt_part[3 * (int64_t)t + f] : 0;
+        }
+    };
+    load_tiles(t0 + (int)threadIdx.x);
     const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.hist_stride;
     // four consecutive bins per thread: one 16-byte load from each of the 16 copies, all issued
     // before any is summed (the pass is latency-bound); bins at or past n are never written and are
@@ -163,6 +180,25 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
             if (v0 + u < d.n) hs[v0 + u] = sum[u];
+    }
+    for (int tb = t0 + (int)threadIdx.x;;) {
+#pragma unroll
+        for (int u = 0; u < kTiles; ++u)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) cc[f] += tv[u][f];
+        tb += 1024 * kTiles;
+        if (tb >= t1) break;
+        load_tiles(tb);
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) cc[f] += __shfl_xor(cc[f], o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        tally[threadIdx.x >> 6][0] = cc[0];
+        tally[threadIdx.x >> 6][1] = cc[1];
+        tally[threadIdx.x >> 6][2] = cc[2];
     }
     __syncthreads();
     const int nb = d.n - 1;                     // bins w = 1 .. n-1, walked from the top
@@ -193,6 +229,15 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
         w.state[b].m_eq = res[2];
         w.state[b].fast = fast ? 1 : 0;
         w.state[b].ncand = fast ? (int32_t)(c_gt + ties) : (int32_t)K;
+        int tb = 0, te = 0, tn = 0;
+        for (int v = 0; v < 16; ++v) {
+            tb += tally[v][0];
+            te += tally[v][1];
+            tn |= tally[v][2];
+        }
+        w.state[b].n_boundary = tb;
+        w.state[b].n_edges = te;
+        w.state[b].nonfinite = tn != 0;
     }
 }
 
@@ -450,7 +495,6 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
 {
     extern __shared__ uint64_t keys[];
     __shared__ int32_t part[kSortWaves][64];
-    __shared__ int32_t tally[kSortWaves][3];
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -490,41 +534,6 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
 #pragma unroll
         for (int u = 0; u < 8; ++u)
             if (k0 + kSortThreads * u < K16) keys[k0 + kSortThreads * u] = v[u];
-    }
-    if (g == 0) {   // the pair's first workgroup: boundary pairs, edges and non-finite input over its tiles
-        const int t0 = stage_first(w, kCompat, b), t1 = t0 + stage_count(w, kCompat, b);
-        int c[3] = {0, 0, 0};
-        for (int tb = t0 + tid; tb < t1; tb += kSortThreads * 8) {   // eight tiles per thread loaded before any is added
-            int v[8][3];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = tb + kSortThreads * u;
-#pragma unroll
-                for (int f = 0; f < 3; ++f) v[u][f] = t < t1 ? w.cnt_part[3 * (int64_t)t + f] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int f = 0; f < 3; ++f) c[f] += v[u][f];
-        }
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) c[f] += __shfl_xor(c[f], o, 64);
-        }
-        if (lane == 0) {
-            tally[wv][0] = c[0];
-            tally[wv][1] = c[1];
-            tally[wv][2] = c[2];
-        }
-        __syncthreads();
-        if (tid < 3) {
-            int t = 0;
-            for (int v = 0; v < kSortWaves; ++v) t += tally[v][tid];
-            if (tid == 0) atomicAdd(&w.state[b].n_boundary, t);
-            else if (tid == 1) atomicAdd(&w.state[b].n_edges, t);
-            else if (t) atomicOr(&w.state[b].nonfinite, 1);
-        }
     }
     __syncthreads();
     const int p = g * 64 + lane;
