@@ -8,7 +8,7 @@
 namespace tr {
 
 constexpr int kSc2Tile = 256;     // output tile edge of the FP4 MFMA SC2 kernel; npad is a multiple
-constexpr int kHistGroups = 16;   // SC2 tiles add their weight histograms into this many copies per pair
+constexpr int kHistGroups = 8;    // SC2 tiles add their weight histograms into this many copies per pair
 constexpr int kCompatTile = 64;   // tile edge of the compatibility kernel
 constexpr int kRowsPerItem = 4;   // rows per work item of the pivot scans (one per wave)
 constexpr int kPrepRows = 256;    // rows per work item of the prep / feature kernels

@@ -162,23 +162,29 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     };
     load_tiles(t0 + (int)threadIdx.x);
     const int32_t *gh = w.ghist + (int64_t)b * kHistGroups * w.hist_stride;
-    // four consecutive bins per thread: one 16-byte load from each of the 16 copies, all issued
-    // before any is summed (the pass is latency-bound); bins at or past n are never written and are
-    // not summed (the copies are padded to a multiple of 8)
-    for (int v0 = 4 * threadIdx.x; v0 < d.n; v0 += 4 * 1024) {
-        int4 c[kHistGroups];
-#pragma unroll
-        for (int g = 0; g < kHistGroups; ++g) c[g] = *reinterpret_cast<const int4 *>(gh + (int64_t)g * w.hist_stride + v0);
-        int32_t sum[4] = {0, 0, 0, 0};
+    // eight consecutive bins per thread: two 16-byte loads from each copy, all issued before any is
+    // summed (the pass is latency-bound: one round up to N = 8192); bins at or past n are never
+    // written and are not summed (the copies are padded to a multiple of 8)
+    for (int v0 = 8 * threadIdx.x; v0 < d.n; v0 += 8 * 1024) {
+        int4 c[kHistGroups][2];
 #pragma unroll
         for (int g = 0; g < kHistGroups; ++g) {
-            sum[0] += c[g].x;
-            sum[1] += c[g].y;
-            sum[2] += c[g].z;
-            sum[3] += c[g].w;
+            c[g][0] = *reinterpret_cast<const int4 *>(gh + (int64_t)g * w.hist_stride + v0);
+            c[g][1] = *reinterpret_cast<const int4 *>(gh + (int64_t)g * w.hist_stride + v0 + 4);
+        }
+        int32_t sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int g = 0; g < kHistGroups; ++g) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                sum[4 * h] += c[g][h].x;
+                sum[4 * h + 1] += c[g][h].y;
+                sum[4 * h + 2] += c[g][h].z;
+                sum[4 * h + 3] += c[g][h].w;
+            }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 8; ++u)
             if (v0 + u < d.n) hs[v0 + u] = sum[u];
     }
     for (int tb = t0 + (int)threadIdx.x;;) {
