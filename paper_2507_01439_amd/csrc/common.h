@@ -235,7 +235,7 @@ hipError_t launch_plan(const Work &w, const int32_t *offsets, int32_t n_single, 
                        hipStream_t s);
 hipError_t launch_compat(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
-hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
+hipError_t launch_pivots(const Work &w, int B, int grid_rows, int grid_emit, hipStream_t s);
 hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
 hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s);
 hipError_t launch_fit_triplets(const float *src, const float *dst, int n, const int32_t *tri, int T, float *poses,

@@ -398,6 +398,7 @@ __global__ void __launch_bounds__(256) k_emit(Work w)
     __shared__ int32_t rowpre[kRowsPerItem][2];
     const int total = stage_total(w, kRowBlk);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (w.n1 && w.state[0].fast) return;   // one pair on the fast path: nothing to emit
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int blk;
         const int b = stage_pair(w, kRowBlk, item, blk);
@@ -577,11 +578,13 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
 
 }  // namespace
 
-hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s)
+// grid_rows: workgroups of the row scan; grid_emit: of the ordered emission (a launch that only
+// exits on the fast path costs less with fewer workgroups)
+hipError_t launch_pivots(const Work &w, int B, int grid_rows, int grid_emit, hipStream_t s)
 {
     hipLaunchKernelGGL(k_thresh, dim3(B), dim3(1024), (size_t)w.max_n * sizeof(int32_t), s, w);
     hipLaunchKernelGGL(k_rowscan, dim3(grid_rows), dim3(256), 0, s, w);
-    hipLaunchKernelGGL(k_emit, dim3(grid_rows), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_emit, dim3(grid_emit), dim3(256), 0, s, w);
     const int bpp = (w.pool_cap + 63) / 64;   // the fast path may rank up to pool_cap keys
     hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(kSortThreads), (size_t)((w.pool_cap + 15) & ~15) * sizeof(uint64_t),
                        s, w, bpp);

@@ -246,7 +246,7 @@ tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_
     }
     if (features_only) return e == hipSuccess ? TR_OK : TR_ERR_HIP;
     mark(TR_STAGE_PIVOTS);
-    chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
+    chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), w.n1 ? grid_cap(h, rows_items, 1) : grid_cap(h, rows_items, 8), s));
     mark(TR_STAGE_LEARNED);
     if (w.learned) {
         // features and scores of the pool's endpoints, then the reorder of the pool
