@@ -75,10 +75,10 @@ struct Work {
     int32_t hist_stride;      // max_n rounded up to 8 (16-byte aligned copies)
     int32_t *rowmax;          // max_batch x max_n: max_{j>i} G_ij (filled by the SC2 epilogue)
     int32_t *cnt_part;        // per compatibility work item: (boundary pairs, edges, non-finite input)
-    int32_t *rowcnt;          // max_batch x max_n x 2 (count > alpha, count == alpha)
+    int32_t *rowcnt;          // max_batch x max_n: pairs of weight alpha per row (ordered path)
     uint64_t *rowseg;         // max_batch x max_n: bit s set if the row's s-th 512-column segment (counted
-                              // from its first column j > i) holds a pair of weight >= alpha
-    int32_t *blkcnt;          // max_batch x nblk x 2
+                              // from its first column j > i) holds a pair of weight alpha (ordered path)
+    int32_t *blkcnt;          // max_batch x nblk: pairs of weight alpha per block of kRowsPerItem rows
     int32_t nblk_stride;      // blocks of kRowsPerItem rows per pair (for max_n)
     uint64_t *cand;           // max_batch x kCollectRegions x pool_cap selection candidates (sort keys); the
                               // ordered path writes region 0 only
@@ -235,7 +235,7 @@ hipError_t launch_plan(const Work &w, const int32_t *offsets, int32_t n_single, 
                        hipStream_t s);
 hipError_t launch_compat(const Work &w, int grid, hipStream_t s);
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s);
-hipError_t launch_pivots(const Work &w, int B, int grid_rows, int grid_emit, hipStream_t s);
+hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s);
 hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s);
 hipError_t launch_hyp(const Work &w, int B, int ppw, int grid, hipStream_t s);
 hipError_t launch_fit_triplets(const float *src, const float *dst, int n, const int32_t *tri, int T, float *poses,

@@ -11,15 +11,15 @@
 //   k_thresh   sums the histograms; finds alpha, the pairs heavier than it
 //              (c_gt) and the ties to take (m); sums the compatibility
 //              kernel's per-tile counts (boundary pairs, edges, non-finite)
-//   k_rowscan  fast path: collects every pair of weight >= alpha (when they
-//              fit the pool) for the sort; ordered path: per row, pairs
-//              > alpha and == alpha; per row block, their sums
-//   k_emit     every row writes its keys at its own offset, in row-major order:
-//              the > alpha keys first, then the first m ties (already in order)
+//   k_rowscan  collects every pair of weight >= alpha when they fit the pool
+//              (fast path), else the pairs heavier than alpha and, per row and
+//              per row block, the count of pairs of weight alpha (ordered path)
 //   k_sort     ranks the collected keys by (w desc, i asc, j asc) and keeps
-//              the first K
-// The key set is exact on both paths and the sort decides every position, so
-// the pivot list does not depend on the order atomics were served in.
+//              the first K; on the ordered path it places the first m ties in
+//              row-major order after the c_gt heavier pairs
+// The key set is exact on both paths and every position is decided by a rank
+// or a row-major tie index, so the pivot list does not depend on the order
+// atomics were served in.
 #include "common.h"
 
 namespace tr {
@@ -55,39 +55,6 @@ __device__ __forceinline__ int wave_incl_scan(int x)
     x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
     return x;
-}
-
-// Counts of one 16-byte chunk of a G row: pairs (i, j), j in 8c .. 8c+7 inside
-// i < j < n, heavier than alpha (low half) and equal to it (high half).
-__device__ __forceinline__ int chunk_counts(const uint4 q, int c, int i, int n, int alpha, bool &hit)
-{
-    const uint32_t u[4] = {q.x, q.y, q.z, q.w};
-    int g = 0, e = 0;
-    hit = false;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int v = (int)((u[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
-        const int j = 8 * c + k;
-        const bool in = j > i && j < n;
-        g += in && v > alpha;
-        e += in && v == alpha;
-        hit |= in && v >= alpha;
-    }
-    return g | (e << 16);
-}
-
-template <typename T>
-__device__ T block_sum(T v, T *lds)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) lds[wid] = v;
-    __syncthreads();
-    T s = 0;
-    for (int k = 0; k < nw; ++k) s += lds[k];
-    __syncthreads();
-    return s;
 }
 
 template <typename T>
@@ -253,24 +220,26 @@ constexpr int kCollectCap = 2048;   // keys a workgroup stages in LDS before its
 
 // One row (i, j > i) of the O2Graph per wave, all of its 16-byte chunks of
 // weights loaded before any is used (the pass is latency-bound); rows whose
-// maximum is below alpha are not read.
+// maximum is below alpha are not read. Each chunk gives two 8-bit masks: the
+// pairs (inside i < j < n) heavier than alpha and those equal to it.
 //
-// Fast path (every pair of weight >= alpha fits the pool): the pairs of
-// weight >= alpha are appended to the pool in no particular order; their
-// count is exactly c_gt + (pairs of weight alpha), and the rank sort fixes the
-// order. A workgroup stages its keys in LDS, reserves its range of the pool
-// with one atomic and copies them out; if its rows hold more than
-// kCollectCap keys it reserves the count first and writes straight to the
-// pool on a second read of those rows.
+// Collected keys: on the fast path (every pair of weight >= alpha fits the
+// pool) the pairs of weight >= alpha, on the ordered path the pairs heavier
+// than alpha (there are c_gt < K of them); either way they are appended to the
+// workgroup's XCD region of the pool in no particular order and the rank sort
+// fixes the order. A workgroup stages its keys in LDS, reserves its range with
+// one atomic and copies them out; if its rows hold more than kCollectCap keys
+// it reserves the count first and writes straight to the pool on a second
+// read of those rows.
 //
-// Ordered path: per row, the pairs heavier than alpha and equal to it and a
-// mask of the 512-column segments holding any of them; per row block, their
-// sums (the emission kernel then writes every key at its final position).
+// Ordered path, besides: per row, the pairs of weight alpha and a mask of the
+// 512-column segments holding any; per row block, their sum. The sort kernel
+// locates the first m ties in row-major order from these.
 __global__ void __launch_bounds__(256) k_rowscan(Work w)
 {
     __shared__ uint64_t buf[kCollectCap];
     __shared__ int32_t nbuf, base;
-    __shared__ int32_t part[4][2];
+    __shared__ int32_t part[4];
     const int total = stage_total(w, kRowBlk);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -279,6 +248,7 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
         const PairState st = w.state[b];
         const PairDesc d = pair_desc(w, b);
         if (d.kpiv <= 0) continue;   // same for the whole workgroup
+        const bool ordered = !st.fast;
         const int alpha = st.alpha, c1 = (d.n + 7) >> 3;
         const int i = blk * kRowsPerItem + wv;
         const int rm = i < d.n ? w.rowmax[(int64_t)b * w.max_n + i] : 0;
@@ -288,9 +258,10 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
         // the pool region and counter of this workgroup's XCD (workgroup g runs on XCD g mod 8)
         const int rgn = blockIdx.x & (kCollectRegions - 1);
         uint64_t *cand = w.cand + ((int64_t)b * kCollectRegions + rgn) * w.pool_cap;
-        // mode 0: count (ordered path); 1: stage into buf; 2: write cand[base + ...]
-        auto scan = [&](int mode, int &cnt, uint64_t &segs) {
-            cnt = 0;
+        // direct = false: stage the keys into buf; true: write cand[base + ...]. ties / segs: the
+        // lane's pairs of weight alpha and the segments holding any (ordered path)
+        auto scan = [&](bool direct, int &ties, uint64_t &segs) {
+            ties = 0;
             segs = 0;
             for (int c0 = c_lo; c0 < c1; c0 += 1024) {
                 uint4 q[16];
@@ -304,21 +275,28 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
                 for (int u = 0; u < 16; ++u) {
                     if (u >= steps) continue;   // uniform: the loop stays unrolled
                     const int c = c0 + 64 * u + lane;
-                    if (mode == 0) {
-                        bool hit = false;
-                        if (c < c1) cnt += chunk_counts(q[u], c, i, d.n, alpha, hit);
-                        if (__any(hit)) segs |= 1ull << ((c0 - c_lo) / 64 + u);   // at most 64 segments (N < 32768)
-                        continue;
-                    }
-                    // bit e: pair (i, 8c + e) lies in i < j < n and weighs at least alpha
+                    // bit e: pair (i, 8c + e) lies in i < j < n and weighs more than / exactly alpha
                     const int lo = min(max(i + 1 - 8 * c, 0), 8), hi = min(max(d.n - 8 * c, 0), 8);
+                    const uint32_t range = ((1u << hi) - 1u) & ~((1u << lo) - 1u);
                     const uint32_t uw[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-                    uint32_t hits = 0;
+                    uint32_t hge = 0, heq = 0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        hits |= ((uint32_t)((int)(uw[k] & 0xFFFFu) >= alpha) << (2 * k)) |
-                                ((uint32_t)((int)(uw[k] >> 16) >= alpha) << (2 * k + 1));
-                    hits &= ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                        hge |= ((uint32_t)((int)(uw[k] & 0xFFFFu) >= alpha) << (2 * k)) |
+                               ((uint32_t)((int)(uw[k] >> 16) >= alpha) << (2 * k + 1));
+                    hge &= range;
+                    if (ordered) {   // the same on the whole workgroup
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            heq |= ((uint32_t)((int)(uw[k] & 0xFFFFu) == alpha) << (2 * k)) |
+                                   ((uint32_t)((int)(uw[k] >> 16) == alpha) << (2 * k + 1));
+                        heq &= range;
+                        if (!direct) {
+                            ties += __builtin_popcount(heq);
+                            if (__any(heq != 0)) segs |= 1ull << ((c0 - c_lo) / 64 + u);   // at most 64 segments (N < 32768)
+                        }
+                    }
+                    const uint32_t hits = hge & ~heq;   // fast path: heq is 0
                     if (!__any(hits != 0)) continue;   // most chunks hold no key
                     const int m = __builtin_popcount(hits);
                     const int incl = wave_incl_scan(m);
@@ -332,7 +310,7 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
                             if ((hits >> e) & 1u) {
                                 const uint32_t v = (uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
                                 const uint64_t key = pivot_key(v, i, 8 * c + e);
-                                if (mode == 2) {
+                                if (direct) {
                                     if (base + off < w.pool_cap) cand[base + off] = key;
                                 } else if (off < kCollectCap) {
                                     buf[off] = key;
@@ -344,16 +322,15 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
                 }
             }
         };
-        int cnt;
-        uint64_t segs;
-        if (st.fast) {
-            if (tid == 0) nbuf = 0;
-            __syncthreads();
-            if (live) scan(1, cnt, segs);
-            __syncthreads();
-            const int n_wg = nbuf;
-            __syncthreads();   // every thread has read nbuf before it is reset
-            if (n_wg == 0) continue;
+        int ties = 0, unused = 0;
+        uint64_t segs = 0, unused_segs = 0;
+        if (tid == 0) nbuf = 0;
+        __syncthreads();
+        if (live) scan(false, ties, segs);
+        __syncthreads();
+        const int n_wg = nbuf;
+        __syncthreads();   // every thread has read nbuf before it is reset
+        if (n_wg > 0) {
             if (tid == 0) base = atomicAdd(&w.tick[(int64_t)b * w.tick_stride + rgn * kTickLine], n_wg);
             __syncthreads();
             if (n_wg <= kCollectCap) {
@@ -362,139 +339,40 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
             } else {
                 if (tid == 0) nbuf = 0;
                 __syncthreads();
-                if (live) scan(2, cnt, segs);
+                if (live) scan(true, unused, unused_segs);
             }
-            __syncthreads();   // buf, nbuf and base are the next item's
-        } else {
-            cnt = 0;
-            segs = 0;
-            if (live) scan(0, cnt, segs);
-            cnt = __builtin_amdgcn_readlane(wave_incl_scan(cnt), 63);
-            const int cg = cnt & 0xFFFF, ce = cnt >> 16;
+        }
+        if (ordered) {
+            ties = __builtin_amdgcn_readlane(wave_incl_scan(ties), 63);
             if (lane == 0) {
                 if (i < d.n) {
-                    w.rowcnt[((int64_t)b * w.max_n + i) * 2] = cg;
-                    w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] = ce;
+                    w.rowcnt[(int64_t)b * w.max_n + i] = ties;
                     w.rowseg[(int64_t)b * w.max_n + i] = segs;
                 }
-                part[wv][0] = cg;
-                part[wv][1] = ce;
+                part[wv] = ties;
             }
             __syncthreads();
-            if (tid < 2)
-                w.blkcnt[((int64_t)b * w.nblk_stride + blk) * 2 + tid] = part[0][tid] + part[1][tid] + part[2][tid] +
-                                                                          part[3][tid];
-            __syncthreads();
+            if (tid == 0) w.blkcnt[(int64_t)b * w.nblk_stride + blk] = part[0] + part[1] + part[2] + part[3];
         }
-    }
-}
-
-// ---------------------------------------------------------------- ordered emission
-
-// Write every pivot's key at its final rank among (> alpha) or (== alpha) pairs.
-__global__ void __launch_bounds__(256) k_emit(Work w)
-{
-    __shared__ int64_t lds[17];
-    __shared__ int32_t rowpre[kRowsPerItem][2];
-    const int total = stage_total(w, kRowBlk);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (w.n1 && w.state[0].fast) return;   // one pair on the fast path: nothing to emit
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int blk;
-        const int b = stage_pair(w, kRowBlk, item, blk);
-        const PairState st = w.state[b];
-        const PairDesc d = pair_desc(w, b);
-        if (st.fast || d.kpiv <= 0) continue;   // same for the whole workgroup
-        // counts of all earlier blocks of this pair
-        int64_t pg = 0, pe = 0;
-        for (int k = threadIdx.x; k < blk; k += 256) {
-            pg += w.blkcnt[((int64_t)b * w.nblk_stride + k) * 2];
-            pe += w.blkcnt[((int64_t)b * w.nblk_stride + k) * 2 + 1];
-        }
-        const int64_t tg = block_sum<int64_t>(pg, lds);
-        const int64_t te = block_sum<int64_t>(pe, lds);
-        if (threadIdx.x < 64) {   // the block's row counts, loaded at once, scanned in the first wave
-            const int rr = threadIdx.x, i = blk * kRowsPerItem + rr;
-            const bool in = rr < kRowsPerItem && i < d.n;
-            const int cg = in ? w.rowcnt[((int64_t)b * w.max_n + i) * 2] : 0;
-            const int ce = in ? w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1] : 0;
-            const int64_t g = tg + wave_excl_scan(cg, rr), e = te + wave_excl_scan(ce, rr);
-            if (rr < kRowsPerItem) {
-                rowpre[rr][0] = (int32_t)g;
-                rowpre[rr][1] = (int32_t)(e < 0x7fffffff ? e : 0x7fffffff);
-            }
-        }
-        __syncthreads();
-        uint64_t *cand = w.cand + (int64_t)b * kCollectRegions * w.pool_cap;   // region 0
-        const int c1 = (d.n + 7) >> 3;
-        for (int rr = 0; rr < kRowsPerItem / 4; ++rr) {
-            const int lr = wv * (kRowsPerItem / 4) + rr, i = blk * kRowsPerItem + lr;
-            if (i >= d.n) break;
-            const int ng = w.rowcnt[((int64_t)b * w.max_n + i) * 2];
-            const int ne = w.rowcnt[((int64_t)b * w.max_n + i) * 2 + 1];
-            int rg = rowpre[lr][0], re = rowpre[lr][1];
-            const int gend = rg + ng;
-            const int eend = min(re + ne, st.m_eq);
-            if (rg >= gend && re >= eend) continue;
-            const uint16_t *row = w.G + d.g_off + (int64_t)i * d.npad;
-            uint64_t todo = w.rowseg[(int64_t)b * w.max_n + i];
-            const int c_lo = (i + 1) >> 3;
-            // only segments that hold a pair of weight >= alpha are read, eight at a time
-            while (todo && (rg < gend || re < eend)) {
-                uint4 q[8];
-                int cs[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    int c = -1;
-                    if (todo) {
-                        c = c_lo + 64 * __builtin_ctzll(todo) + lane;
-                        todo &= todo - 1;
-                    }
-                    cs[u] = c;
-                    q[u] = (c >= 0 && c < c1) ? *reinterpret_cast<const uint4 *>(row + 8 * c) : make_uint4(0, 0, 0, 0);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int c = cs[u];
-                    if (__builtin_amdgcn_readfirstlane(c) < 0) break;   // no segment left (same on every lane)
-                    bool hit;
-                    const int cnt = c < c1 ? chunk_counts(q[u], c, i, d.n, st.alpha, hit) : 0;
-                    const int incl = wave_incl_scan(cnt);
-                    const int excl = incl - cnt, tot = __builtin_amdgcn_readlane(incl, 63);
-                    if (cnt) {
-                        int og = rg + (excl & 0xFFFF), oe = re + (excl >> 16);
-                        const uint32_t uw[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const int j = 8 * c + e;
-                            if (!(j > i && j < d.n)) continue;
-                            const int v = (int)((uw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-                            if (v > st.alpha) {   // c_gt bounds the writes whatever G holds
-                                if (og < st.c_gt) cand[og] = pivot_key(v, i, j);
-                                ++og;
-                            } else if (v == st.alpha) {
-                                if (oe < st.m_eq) cand[st.c_gt + oe] = pivot_key(v, i, j);
-                                ++oe;
-                            }
-                        }
-                    }
-                    rg += tot & 0xFFFF;
-                    re += tot >> 16;
-                }
-            }
-        }
-        __syncthreads();
+        __syncthreads();   // buf, nbuf, base and part are the next item's
     }
 }
 
 // ---------------------------------------------------------------- ordering
 
-// Order the K keys of one pair by (w desc, i asc, j asc) and write (i, j, w).
+// Order the K pivots of one pair by (w desc, i asc, j asc) and write (i, j, w).
 // Keys are distinct, so a key's rank is the number of smaller keys. Each
-// workgroup of kSortWaves waves copies the pair's K keys into its LDS and
-// ranks 64 of them: wave v counts the smaller keys in its slice of the list
-// with eight 16-byte broadcast reads in flight, and the partial counts are
-// summed. The work of one pair is spread over ceil(K/64) CUs.
+// workgroup of kSortWaves waves copies the pair's collected keys into its LDS
+// and ranks 64 of them: wave v counts the smaller keys in its slice of the
+// list with eight 16-byte broadcast reads in flight, and the partial counts
+// are summed. The work of one pair is spread over ceil(K/64) CUs.
+//
+// Ordered path: the collected keys are the c_gt pairs heavier than alpha and
+// fill slots 0 .. c_gt-1; slot c_gt + t holds the t-th pair of weight alpha in
+// row-major order. A workgroup whose 64 slots reach past c_gt finds its ties
+// from the row scan's counts: an exclusive scan of the per-block tie counts
+// names the (at most 64) blocks that hold them, and one wave per block walks
+// its rows' segments, counting ties in order, and writes those in its range.
 constexpr int kSortWaves = 16;
 constexpr int kSortThreads = 64 * kSortWaves;
 
@@ -502,6 +380,8 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
 {
     extern __shared__ uint64_t keys[];
     __shared__ int32_t part[kSortWaves][64];
+    __shared__ int64_t lds[17];
+    __shared__ int32_t nrel, rel_blk[64], rel_pre[64];
     const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -510,19 +390,14 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
 #pragma unroll
     for (int r = 0; r < kCollectRegions; ++r) c[r] = w.tick[(int64_t)b * w.tick_stride + r * kTickLine];
     const PairState st = w.state[b];
-    // the keys sit in the kCollectRegions regions of the pool (fast path: the count of each is its
-    // counter) or in region 0 (ordered path: exactly K)
+    // the keys sit in the kCollectRegions regions of the pool, as many in each as its counter says
     int rb[kCollectRegions + 1];
     rb[0] = 0;
-    if (K > 0 && st.fast) {
 #pragma unroll
-        for (int r = 0; r < kCollectRegions; ++r) rb[r + 1] = rb[r] + min(max(c[r], 0), w.pool_cap);
-    } else {
-#pragma unroll
-        for (int r = 0; r < kCollectRegions; ++r) rb[r + 1] = K > 0 ? st.ncand : 0;
-    }
-    // keys ranked (the first K are kept)
-    const int NC = K > 0 ? min(min(st.ncand, rb[kCollectRegions]), w.pool_cap) : 0;
+    for (int r = 0; r < kCollectRegions; ++r) rb[r + 1] = rb[r] + min(max(c[r], 0), w.pool_cap);
+    // keys ranked (the first K are kept): fast path c_gt + all ties, ordered path c_gt
+    const int want = K > 0 ? (st.fast ? st.ncand : st.c_gt) : 0;
+    const int NC = min(min(want, rb[kCollectRegions]), w.pool_cap);
     int32_t *out = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
     if (g * 64 >= max(NC, w.pool)) return;
     const uint64_t *cand = w.cand + (int64_t)b * kCollectRegions * w.pool_cap;
@@ -545,46 +420,141 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
     __syncthreads();
     const int p = g * 64 + lane;
     const uint64_t mine = p < NC ? keys[p] : 0;
-    const int per = ((K16 / 16 + kSortWaves - 1) / kSortWaves) * 16;   // a slice of whole 16-key groups
-    const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
-    int r = 0;
-    for (int q = q0; q < q1; q += 16) {
-        uint4 a[8];
+    if (g * 64 < NC) {   // the same on the whole workgroup
+        const int per = ((K16 / 16 + kSortWaves - 1) / kSortWaves) * 16;   // a slice of whole 16-key groups
+        const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
+        int r = 0;
+        for (int q = q0; q < q1; q += 16) {
+            uint4 a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const uint4 *>(&keys[q + 2 * u]);
+            for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const uint4 *>(&keys[q + 2 * u]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            r += (((uint64_t)a[u].y << 32) | a[u].x) < mine;
-            r += (((uint64_t)a[u].w << 32) | a[u].z) < mine;
+            for (int u = 0; u < 8; ++u) {
+                r += (((uint64_t)a[u].y << 32) | a[u].x) < mine;
+                r += (((uint64_t)a[u].w << 32) | a[u].z) < mine;
+            }
+        }
+        part[wv][lane] = r;
+        __syncthreads();
+        if (wv == 0) {
+            int rk = 0;
+#pragma unroll
+            for (int v = 0; v < kSortWaves; ++v) rk += part[v][lane];
+            if (p < NC && rk < K) {
+                out[3 * rk] = (int32_t)((mine >> 20) & 0xFFFFF);
+                out[3 * rk + 1] = (int32_t)(mine & 0xFFFFF);
+                out[3 * rk + 2] = (int32_t)(0xFFFFu - (uint32_t)(mine >> 40));
+            }
         }
     }
-    part[wv][lane] = r;
-    __syncthreads();
-    if (wv != 0) return;
-    int rk = 0;
-#pragma unroll
-    for (int v = 0; v < kSortWaves; ++v) rk += part[v][lane];
-    if (p < NC && rk < K) {
-        out[3 * rk] = (int32_t)((mine >> 20) & 0xFFFFF);
-        out[3 * rk + 1] = (int32_t)(mine & 0xFFFFF);
-        out[3 * rk + 2] = (int32_t)(0xFFFFu - (uint32_t)(mine >> 40));
-    }
-    if (p >= K && p < w.pool) {   // slots past the pair's pivots
+    if (wv == 0 && p >= K && p < w.pool) {   // slots past the pair's pivots
         out[3 * p] = -1;
         out[3 * p + 1] = -1;
         out[3 * p + 2] = 0;
+    }
+    if (K <= 0 || st.fast) return;
+    // ordered path: ties t0 .. t1-1 of this workgroup's slots
+    const int cgt = st.c_gt, alpha = st.alpha;
+    const int t0 = max(g * 64, cgt) - cgt, t1 = min(g * 64 + 64, K) - cgt;
+    if (t1 <= t0) return;
+    const int nblk = (d.n + kRowsPerItem - 1) / kRowsPerItem;
+    const int32_t *bc = w.blkcnt + (int64_t)b * w.nblk_stride;
+    int bcnt[8];
+    int64_t local = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {   // blocks 8t .. 8t+7 per thread (nblk <= 8192)
+        const int k = 8 * tid + u;
+        bcnt[u] = k < nblk ? bc[k] : 0;
+        local += bcnt[u];
+    }
+    if (tid == 0) nrel = 0;
+    int64_t total;
+    int64_t run = block_exclusive_scan<int64_t>(local, lds, total);   // its barriers order nrel's reset
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        if (bcnt[u] > 0 && run < t1 && run + bcnt[u] > t0) {   // the block holds a tie of the range
+            const int slot = atomicAdd(&nrel, 1);
+            if (slot < 64) {
+                rel_blk[slot] = 8 * tid + u;
+                rel_pre[slot] = (int32_t)run;
+            }
+        }
+        run += bcnt[u];
+    }
+    __syncthreads();
+    const int nr = min(nrel, 64);
+    const uint16_t *G = w.G + d.g_off;
+    const int c1 = (d.n + 7) >> 3;
+    for (int x = wv; x < nr; x += kSortWaves) {
+        int pre = rel_pre[x];
+        const int blk = rel_blk[x];
+        for (int rr = 0; rr < kRowsPerItem; ++rr) {
+            const int i = blk * kRowsPerItem + rr;
+            if (i >= d.n || pre >= t1) break;
+            const int ne = w.rowcnt[(int64_t)b * w.max_n + i];
+            if (ne > 0 && pre + ne > t0) {
+                // the row's ties in order, eight segments (512 columns each) loaded at a time
+                const uint16_t *row = G + (int64_t)i * d.npad;
+                const int c_lo = (i + 1) >> 3;
+                uint64_t todo = w.rowseg[(int64_t)b * w.max_n + i];
+                int idx0 = pre;   // tie index of the row's next tie
+                while (todo && idx0 < t1) {
+                    uint4 q[8];
+                    int cs[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        int cc = -1;
+                        if (todo) {
+                            cc = c_lo + 64 * __builtin_ctzll(todo) + lane;
+                            todo &= todo - 1;
+                        }
+                        cs[u] = cc;
+                        q[u] = (cc >= 0 && cc < c1) ? *reinterpret_cast<const uint4 *>(row + 8 * cc)
+                                                    : make_uint4(0, 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int cc = cs[u];
+                        if (__builtin_amdgcn_readfirstlane(cc) < 0) break;   // no segment left (the same on every lane)
+                        const int lo = min(max(i + 1 - 8 * cc, 0), 8), hi = min(max(d.n - 8 * cc, 0), 8);
+                        const uint32_t uw[4] = {q[u].x, q[u].y, q[u].z, q[u].w};
+                        uint32_t heq = 0;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            heq |= ((uint32_t)((int)(uw[k] & 0xFFFFu) == alpha) << (2 * k)) |
+                                   ((uint32_t)((int)(uw[k] >> 16) == alpha) << (2 * k + 1));
+                        heq &= ((1u << hi) - 1u) & ~((1u << lo) - 1u);
+                        const int m = __builtin_popcount(heq);
+                        const int incl = wave_incl_scan(m);
+                        int idx = idx0 + incl - m;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            if ((heq >> e) & 1u) {
+                                if (idx >= t0 && idx < t1) {
+                                    const int slot = cgt + idx;   // < K <= pool_cap
+                                    out[3 * slot] = i;
+                                    out[3 * slot + 1] = 8 * cc + e;
+                                    out[3 * slot + 2] = alpha;
+                                }
+                                ++idx;
+                            }
+                        }
+                        idx0 += __builtin_amdgcn_readlane(incl, 63);
+                    }
+                }
+            }
+            pre += ne;
+        }
     }
 }
 
 }  // namespace
 
-// grid_rows: workgroups of the row scan; grid_emit: of the ordered emission (a launch that only
-// exits on the fast path costs less with fewer workgroups)
-hipError_t launch_pivots(const Work &w, int B, int grid_rows, int grid_emit, hipStream_t s)
+// grid_rows: workgroups of the row scan
+hipError_t launch_pivots(const Work &w, int B, int grid_rows, hipStream_t s)
 {
     hipLaunchKernelGGL(k_thresh, dim3(B), dim3(1024), (size_t)w.max_n * sizeof(int32_t), s, w);
     hipLaunchKernelGGL(k_rowscan, dim3(grid_rows), dim3(256), 0, s, w);
-    hipLaunchKernelGGL(k_emit, dim3(grid_emit), dim3(256), 0, s, w);
     const int bpp = (w.pool_cap + 63) / 64;   // the fast path may rank up to pool_cap keys
     hipLaunchKernelGGL(k_sort, dim3(B * bpp), dim3(kSortThreads), (size_t)((w.pool_cap + 15) & ~15) * sizeof(uint64_t),
                        s, w, bpp);

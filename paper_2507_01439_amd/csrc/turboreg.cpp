@@ -246,7 +246,7 @@ tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_
     }
     if (features_only) return e == hipSuccess ? TR_OK : TR_ERR_HIP;
     mark(TR_STAGE_PIVOTS);
-    chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), w.n1 ? grid_cap(h, rows_items, 1) : grid_cap(h, rows_items, 8), s));
+    chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
     mark(TR_STAGE_LEARNED);
     if (w.learned) {
         // features and scores of the pool's endpoints, then the reorder of the pool
@@ -383,8 +383,8 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
         const size_t nb64 = h->npad_max / kCompatTile;
         A(alloc(h, &h->cnt_part, B * nb64 * (nb64 + 1) / 2 * 3));   // boundary pairs, edges, non-finite flag
     }
-    A(alloc(h, &h->rowcnt, B * max_n * 2));
-    A(alloc(h, &h->blkcnt, B * h->nblk_stride * 2));
+    A(alloc(h, &h->rowcnt, B * max_n));
+    A(alloc(h, &h->blkcnt, B * h->nblk_stride));
     A(alloc(h, &h->cand, B * kCollectRegions * h->pool_cap));
     A(alloc(h, &h->tick, B * h->tick_stride));
     A(alloc(h, &h->hyp_rec, B * h->rec_stride));

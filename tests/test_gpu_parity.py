@@ -123,6 +123,31 @@ def test_fast_collection_past_stage_capacity(reg):
     assert r.n_pivots == 2000
 
 
+def test_ordered_path_heavier_pairs_then_ties():
+    # independent random clouds and a tight tau: weights 0..3, so alpha is 1 (65 heavier pairs,
+    # 1101 ties) or 0 (every non-edge ties); the ties overflow the small pool (8 x max_k1), so the
+    # heavier pairs are ranked and the first ties in row-major order fill the rest, over several
+    # sort workgroups (one of them straddling c_gt)
+    n = 2000
+    rng = np.random.default_rng(91)
+    X = ((rng.random((n, 3)) - 0.5) * 2).astype(np.float32)
+    Y = ((rng.random((n, 3)) - 0.5) * 2).astype(np.float32)
+    tau = 0.006
+    w = oracle.sc2(oracle.compat(X, Y, tau)[0])[np.triu_indices(n, 1)]
+    for max_k1, k1 in ((130, 130), (130, 100), (1500, 1500)):
+        alpha = np.sort(w)[::-1][k1 - 1]
+        c_gt, ties = int((w > alpha).sum()), int((w == alpha).sum())
+        assert 0 < c_gt < k1 and c_gt + ties > 8 * max_k1, (k1, alpha, c_gt, ties)   # the ordered path
+        small = T.Registrar(max_n=n, max_batch=1, max_k1=max_k1, max_k2=2)
+        try:
+            prm = T.make_params(tau, 0.1, k1=k1, k2=2)
+            say(f"ordered path k1={k1} alpha={alpha} c_gt={c_gt} ties={ties}")
+            r, mask = run_single(small, torch, X, Y, prm)
+            check_taps(small, X, Y, prm, r, mask, label=f"ordered k1={k1}")
+        finally:
+            small.close()
+
+
 def test_all_outliers_no_hypothesis(reg):
     p = indoor(300, 0.0, 11)
     prm = T.make_params(1e-4, 0.1, k1=50, k2=2)
