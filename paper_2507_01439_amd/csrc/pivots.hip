@@ -103,8 +103,7 @@ __device__ __forceinline__ void load8(const uint16_t *row, int c, int (&v)[8])
 __global__ void __launch_bounds__(1024) k_thresh(Work w)
 {
     extern __shared__ int32_t hs[];
-    __shared__ int64_t lds[17];
-    __shared__ int32_t res[3];
+    __shared__ int32_t res[3], wtot[16];
     __shared__ int32_t tally[16][3];
     const int b = blockIdx.x;
     const PairDesc d = pair_desc(w, b);
@@ -174,13 +173,26 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
         tally[threadIdx.x >> 6][2] = cc[2];
     }
     __syncthreads();
-    const int nb = d.n - 1;                     // bins w = 1 .. n-1, walked from the top
+    // bins w = 1 .. n-1 walked from the top: thread t sums the contiguous positions u0 .. u1-1
+    // (u = n-1-w); an in-wave scan and the sixteen wave totals give each thread the count above
+    // its range, and the thread whose range holds the K-th largest weight walks it (counts stay
+    // below n(n-1)/2 < 2^31)
+    const int nb = d.n - 1;
     const int cs = (nb + 1023) / 1024;
     const int u0 = min(nb, (int)threadIdx.x * cs), u1 = min(nb, u0 + cs);
-    int64_t local = 0;
+    int local = 0;
     for (int u = u0; u < u1; ++u) local += hs[d.n - 1 - u];
-    int64_t tot;
-    const int64_t excl = block_exclusive_scan<int64_t>(local, lds, tot);
+    const int incl = wave_incl_scan(local);
+    if ((threadIdx.x & 63) == 63) wtot[threadIdx.x >> 6] = incl;
+    __syncthreads();
+    int64_t tot = 0, before = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int t = wtot[v];
+        before += v < (int)(threadIdx.x >> 6) ? t : 0;
+        tot += t;
+    }
+    const int64_t excl = before + incl - local;
     if (threadIdx.x == 0 && K > tot) { res[0] = 0; res[1] = (int32_t)tot; res[2] = (int32_t)(K - tot); }
     if (K <= tot && excl < K && K <= excl + local) {
         int64_t cum = excl;
