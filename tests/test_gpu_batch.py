@@ -111,3 +111,33 @@ def test_batch_success_on_indoor_pairs(reg):
     res = T.parse_results(out, len(ns))
     ok = [synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p) for r, p in zip(res, pairs)]
     assert np.mean(ok) >= 0.9, ok
+
+
+def test_independent_handles_on_two_streams(reg):
+    # registrations on two handles, each on its own stream, interleaved without synchronisation:
+    # every result and mask must equal the same registration run alone on the fixture's handle
+    ns = [1500, 900, 1200, 640, 1500, 1100]
+    pairs = [synth.make_pair(synth.CONFIGS["indoor_n1000"].replace(n=n, inlier_ratio=0.08), synth.pair_seed(2, 900 + b))
+             for b, n in enumerate(ns)]
+    prm = T.make_params(0.1, 0.1, 300, 2)
+    alone = []
+    for p in pairs:
+        out, mask = reg.register(to_dev(torch, p.src), to_dev(torch, p.dst), prm)
+        torch.cuda.synchronize()
+        alone.append((bytes(out.cpu().numpy()), mask.cpu().numpy().copy()))
+    handles = [T.Registrar(max_n=1500, max_batch=1, max_k1=400, max_k2=3) for _ in range(2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
+    try:
+        outs = []
+        inputs = [(to_dev(torch, p.src), to_dev(torch, p.dst)) for p in pairs]
+        torch.cuda.synchronize()
+        for k, (src, dst) in enumerate(inputs):
+            with torch.cuda.stream(streams[k % 2]):
+                outs.append(handles[k % 2].register(src, dst, prm))
+        torch.cuda.synchronize()
+        for k, ((o, m), (ao, am)) in enumerate(zip(outs, alone)):
+            assert bytes(o.cpu().numpy()) == ao, k
+            assert np.array_equal(m.cpu().numpy(), am), k
+    finally:
+        for h in handles:
+            h.close()
