@@ -92,7 +92,9 @@ typedef struct tr_handle tr_handle;
 /* Create a handle on `device` whose workspace holds up to `max_batch` pairs of
  * up to `max_n` matches, K1 <= max_k1 and K2 <= max_k2. Learned mode needs
  * pool_factor*K1 <= min(8*max_k1, TR_MAX_POOL). Allocates device memory
- * (about 2.5 * max_batch * round_up(max_n,256)^2 bytes); max_n <= 32767. *out is NULL on error. */
+ * (about 2.5 * max_batch * round_up(max_n,256)^2 bytes for C and the SC2 weights, plus about
+ * max_batch * (80 * min(8*max_k1, TR_MAX_POOL) + 70 * max_k1 * max_k2) bytes for the pivot pool,
+ * the hypotheses and their counters); max_n <= 32767. *out is NULL on error. */
 tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t max_k1,
                     int32_t max_k2, int32_t device);
 tr_status tr_destroy(tr_handle *h);
