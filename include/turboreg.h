@@ -57,7 +57,8 @@ enum {
      * paper's supplementary Table 6). Over the inliers of Eq. 9 (r^2 <= theta^2), with
      * e = sqrt(r^2) and u = max(0, (theta - e) / theta) in float32, the score is the sum of u (MAE form)
      * or of u*u (MSE form), summed in float32; the largest score wins (lowest h on ties).
-     * best_inliers is still the selected hypothesis's inlier number. At most one of the two. */
+     * best_inliers is still the selected hypothesis's inlier number. At most one of the two;
+     * either needs theta > 0 (TR_ERR_INVALID_ARG otherwise). */
     TR_FLAG_RANK_MAE = 4u,
     TR_FLAG_RANK_MSE = 8u
 };
@@ -132,7 +133,8 @@ tr_status tr_fit_triplets(tr_handle *h, const float *src, const float *dst, int3
  * computed in the same arithmetic and order as the registration's hypothesis scoring, so a
  * hypothesis pose scores the same bits. For evaluating external poses (a ground-truth
  * transformation, poses from another method). TR_ERR_INVALID_ARG for n < 1, P < 0, a negative
- * or non-finite theta, metric outside 0..2 or a missing score buffer. */
+ * or non-finite theta, theta = 0 with metric 1 or 2, metric outside 0..2 or a missing score
+ * buffer. */
 tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32_t n, const float *poses_dev,
                          int32_t P, float theta, int32_t metric, int32_t *in_dev, float *score_dev, void *stream);
 

@@ -15,27 +15,40 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "turboreg_oracle.c")
-_LIB = os.path.join(_HERE, "libturboreg_oracle.so")
-_lib = None
+_LIB = os.path.join(_HERE, "libturboreg_oracle.so")          # one thread
+_LIB_OMP = os.path.join(_HERE, "libturboreg_oracle_omp.so")  # the same code with OpenMP loops
+_libs = {}
+_threaded = False
 
 
 def build() -> str:
-    """Compile the oracle with gcc (no contraction, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-           "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(_LIB + ".tmp", _LIB)
+    """Compile the oracle with gcc (no contraction, no fast-math), once plain and once with
+    OpenMP over the host's cores (same arithmetic: the pragmas only split independent loops)."""
+    base = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-Wall"]
+    for out, extra in ((_LIB, ["-Wno-unknown-pragmas"]), (_LIB_OMP, ["-fopenmp"])):
+        subprocess.run(base + extra + ["-o", out + ".tmp", _SRC, "-lm"], check=True)
+        os.replace(out + ".tmp", out)
     return _LIB
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def set_threaded(flag: bool) -> bool:
+    """Route the functions below to the OpenMP build (True) or the one-thread build; returns the
+    previous setting."""
+    global _threaded
+    prev, _threaded = _threaded, bool(flag)
+    return prev
+
+
+def lib(threaded=None):
+    threaded = _threaded if threaded is None else threaded
+    if threaded not in _libs:
+        path = _LIB_OMP if threaded else _LIB
+        if not os.path.exists(path):
             build()
-        _lib = ct.CDLL(_LIB)
-        _declare(_lib)
-    return _lib
+        L = ct.CDLL(path)
+        _declare(L)
+        _libs[threaded] = L
+    return _libs[threaded]
 
 
 _f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
@@ -197,13 +210,13 @@ def select_score(S):
     return int(lib().tro_select_score(S, S.shape[0]))
 
 
-def register(X, Y, tau, theta, k1, k2, graph=0):
+def register(X, Y, tau, theta, k1, k2, graph=0, threaded=None):
     """Whole path -> (Result, mask)."""
     X, Y = _pts(X), _pts(Y)
     p = Params(tau, theta, k1, k2, graph)
     r = Result()
     m = np.empty(X.shape[0], np.uint8)
-    _check(lib().tro_register(X, Y, X.shape[0], ct.byref(p), ct.byref(r), m.ctypes.data), "register")
+    _check(lib(threaded).tro_register(X, Y, X.shape[0], ct.byref(p), ct.byref(r), m.ctypes.data), "register")
     return r, m
 
 

@@ -10,6 +10,9 @@
  * Build: gcc -O2 -std=c11 -fPIC -shared -ffp-contract=off -fno-fast-math -lm.
  * Floating-point contraction is off so that every a*b and a+b below is one
  * IEEE-rounded operation; fused multiply-adds appear only as explicit fmaf().
+ * A second build adds -fopenmp: the pragmas below split loops whose iterations
+ * write disjoint outputs (integer sums are reduced exactly), so both builds
+ * compute the same bits; without -fopenmp the pragmas are ignored.
  *
  * Every function is pinned by tests that do not reuse this code: brute-force
  * triangle enumeration, closed forms, hand-counted graphs, LAPACK/numpy
@@ -60,6 +63,7 @@ int tro_compat(const float *X, const float *Y, int32_t n, float tau, uint8_t *C,
 {
     if (!X || !Y || !C || n < 0) return -1;
     int64_t nb32 = 0, nb64 = 0, nf = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : nb32, nb64, nf)
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t j = 0; j < n; ++j) {
             if (i == j) { C[(int64_t)i * n + j] = 0; continue; }   /* no self loops (reading) */
@@ -74,9 +78,12 @@ int tro_compat(const float *X, const float *Y, int32_t n, float tau, uint8_t *C,
         }
     }
     /* IEEE subtraction is sign-symmetric, so the matrix must come out symmetric. */
+    int asym = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : asym)
     for (int32_t i = 0; i < n; ++i)
         for (int32_t j = i + 1; j < n; ++j)
-            if (C[(int64_t)i * n + j] != C[(int64_t)j * n + i]) return -2;
+            asym |= C[(int64_t)i * n + j] != C[(int64_t)j * n + i];
+    if (asym) return -2;
     if (n_boundary32) *n_boundary32 = nb32;
     if (n_boundary64) *n_boundary64 = nb64;
     if (n_flip) *n_flip = nf;
@@ -96,9 +103,11 @@ int tro_sc2(const uint8_t *C, int32_t n, int32_t *Ghat)
     int64_t words = ((int64_t)n + 63) / 64;
     uint64_t *bits = (uint64_t *)calloc((size_t)(words * (n > 0 ? n : 1)), sizeof(uint64_t));
     if (!bits) return -3;
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i)
         for (int32_t k = 0; k < n; ++k)
             if (C[(int64_t)i * n + k]) bits[i * words + k / 64] |= (uint64_t)1 << (k % 64);
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t i = 0; i < n; ++i) {
         for (int32_t j = 0; j < n; ++j) {
             int32_t v = 0;
@@ -117,6 +126,7 @@ int tro_sc2(const uint8_t *C, int32_t n, int32_t *Ghat)
 int tro_o2graph(const int32_t *Ghat, int32_t n, int32_t *Gt)
 {
     if (!Ghat || !Gt || n < 0) return -1;
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i)
         for (int32_t j = 0; j < n; ++j)
             Gt[(int64_t)i * n + j] = (i < j) ? Ghat[(int64_t)i * n + j] : 0;
@@ -149,11 +159,14 @@ int64_t tro_pivots(const int32_t *Gbar, int32_t n, int32_t k1, int32_t *P)
 {
     if (!Gbar || !P || n < 0 || k1 < 0) return -1;
     int64_t m = (int64_t)n * (n - 1) / 2, pos = 0;
+    int negative = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pos) reduction(| : negative)
     for (int32_t i = 0; i < n; ++i)
         for (int32_t j = i + 1; j < n; ++j) {
-            if (Gbar[(int64_t)i * n + j] < 0) return -1;
+            negative |= Gbar[(int64_t)i * n + j] < 0;
             pos += Gbar[(int64_t)i * n + j] > 0;
         }
+    if (negative) return -1;
     edge_t *e = (edge_t *)malloc((size_t)(pos > 0 ? pos : 1) * sizeof(edge_t));
     if (!e) return -3;
     int64_t c = 0;
@@ -184,42 +197,49 @@ int tro_cliques(const int32_t *Gbar, int32_t n, const int32_t *P, int32_t n_pivo
                 int32_t k1, int32_t k2, int32_t *cliques)
 {
     if (!Gbar || !P || !cliques || n < 0 || k1 < 0 || k2 < 1 || n_pivots > k1) return -1;
-    int32_t *bs = (int32_t *)malloc(sizeof(int32_t) * (size_t)k2);
-    int32_t *bz = (int32_t *)malloc(sizeof(int32_t) * (size_t)k2);
-    if (!bs || !bz) { free(bs); free(bz); return -3; }
-    for (int32_t p = 0; p < k1; ++p) {
-        for (int32_t s = 0; s < k2; ++s) { bs[s] = -1; bz[s] = -1; }
-        int32_t i = -1, j = -1;
-        if (p < n_pivots) {
-            i = P[3 * p];
-            j = P[3 * p + 1];
-            int32_t gij = Gbar[(int64_t)i * n + j];
-            for (int32_t z = 0; z < n; ++z) {
-                if (z == i || z == j) continue;
-                int32_t giz = Gbar[(int64_t)i * n + z], gjz = Gbar[(int64_t)j * n + z];
-                /* verification condition (Eq. 8): all three weights positive */
-                if (!(gij > 0 && giz > 0 && gjz > 0)) continue;
-                int32_t S = gij + giz + gjz;                     /* Eq. 6 */
-                /* keep the k2 best by (S desc, z asc); z grows, so a tie never displaces */
-                int32_t pos = k2;
-                for (int32_t q = 0; q < k2; ++q)
-                    if (bz[q] < 0 || S > bs[q]) { pos = q; break; }
-                if (pos == k2) continue;
-                for (int32_t q = k2 - 1; q > pos; --q) { bs[q] = bs[q - 1]; bz[q] = bz[q - 1]; }
-                bs[pos] = S;
-                bz[pos] = z;
+    int failed = 0;
+#pragma omp parallel reduction(| : failed)
+    {
+        /* the pivot's K2 best (S, z) so far, one list per thread */
+        int32_t *bs = (int32_t *)malloc(sizeof(int32_t) * (size_t)k2);
+        int32_t *bz = (int32_t *)malloc(sizeof(int32_t) * (size_t)k2);
+        failed |= !bs || !bz;
+#pragma omp for schedule(dynamic, 4)
+        for (int32_t p = 0; p < k1; ++p) {
+            if (!bs || !bz) continue;
+            for (int32_t s = 0; s < k2; ++s) { bs[s] = -1; bz[s] = -1; }
+            int32_t i = -1, j = -1;
+            if (p < n_pivots) {
+                i = P[3 * p];
+                j = P[3 * p + 1];
+                int32_t gij = Gbar[(int64_t)i * n + j];
+                for (int32_t z = 0; z < n; ++z) {
+                    if (z == i || z == j) continue;
+                    int32_t giz = Gbar[(int64_t)i * n + z], gjz = Gbar[(int64_t)j * n + z];
+                    /* verification condition (Eq. 8): all three weights positive */
+                    if (!(gij > 0 && giz > 0 && gjz > 0)) continue;
+                    int32_t S = gij + giz + gjz;                     /* Eq. 6 */
+                    /* keep the k2 best by (S desc, z asc); z grows, so a tie never displaces */
+                    int32_t pos = k2;
+                    for (int32_t q = 0; q < k2; ++q)
+                        if (bz[q] < 0 || S > bs[q]) { pos = q; break; }
+                    if (pos == k2) continue;
+                    for (int32_t q = k2 - 1; q > pos; --q) { bs[q] = bs[q - 1]; bz[q] = bz[q - 1]; }
+                    bs[pos] = S;
+                    bz[pos] = z;
+                }
+            }
+            for (int32_t s = 0; s < k2; ++s) {
+                int64_t h = (int64_t)s * k1 + p;                      /* Algorithm 2 layout */
+                cliques[3 * h] = i;
+                cliques[3 * h + 1] = j;
+                cliques[3 * h + 2] = bz[s];
             }
         }
-        for (int32_t s = 0; s < k2; ++s) {
-            int64_t h = (int64_t)s * k1 + p;                      /* Algorithm 2 layout */
-            cliques[3 * h] = i;
-            cliques[3 * h + 1] = j;
-            cliques[3 * h + 2] = bz[s];
-        }
+        free(bs);
+        free(bz);
     }
-    free(bs);
-    free(bz);
-    return 0;
+    return failed ? -3 : 0;
 }
 
 /* ------------------------------------------------------------------ */
@@ -329,6 +349,7 @@ int tro_kabsch(const float *X, const float *Y, const int32_t *cliques, int32_t H
                double *R, double *t, int32_t *flags)
 {
     if (!X || !Y || !cliques || !R || !t || !flags || H < 0) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t h = 0; h < H; ++h) {
         const int32_t *c = cliques + 3 * (int64_t)h;
         double *Rh = R + 9 * (int64_t)h, *th = t + 3 * (int64_t)h;
@@ -374,6 +395,7 @@ int tro_score(const float *X, const float *Y, int32_t n, const float *poses,
 {
     if (!X || !Y || !poses || !valid || !IN || n < 0 || H < 0) return -1;
     float th2 = theta * theta;
+#pragma omp parallel for schedule(dynamic, 4)
     for (int32_t h = 0; h < H; ++h) {
         if (!valid[h]) { IN[h] = -1; continue; }
         int32_t c = 0;
@@ -413,8 +435,11 @@ int32_t tro_select(const int32_t *IN, int32_t H)
 int tro_score_metric(const float *X, const float *Y, int32_t n, const float *poses,
                      const int32_t *valid, int32_t H, float theta, int32_t metric, float *S)
 {
-    if (!X || !Y || !poses || !valid || !S || n < 0 || H < 0 || (metric != 1 && metric != 2)) return -1;
+    /* theta = 0 leaves u = 0/0 undefined: the error-based rankings need theta > 0 */
+    if (!X || !Y || !poses || !valid || !S || n < 0 || H < 0 || (metric != 1 && metric != 2) || !(theta > 0.0f))
+        return -1;
     const float th2 = theta * theta;
+#pragma omp parallel for schedule(dynamic, 4)
     for (int32_t h = 0; h < H; ++h) {
         if (!valid[h]) { S[h] = -1.0f; continue; }
         double acc = 0.0;
@@ -422,7 +447,10 @@ int tro_score_metric(const float *X, const float *Y, int32_t n, const float *pos
             const float r2 = residual2(poses + 12 * (int64_t)h, X + 3 * (int64_t)k, Y + 3 * (int64_t)k);
             if (!(r2 <= th2)) continue;
             float u = (theta - sqrtf(r2)) / theta;
-            if (u < 0.0f) u = 0.0f;   /* r^2 <= theta^2 can still leave e one ulp above theta */
+            /* e <= theta whenever theta^2 is a normal float32 (a correctly rounded square root of
+             * a correctly rounded square returns the operand); a subnormal theta^2 has lost bits,
+             * and e can then exceed theta: the truncation keeps u at 0 */
+            if (u < 0.0f) u = 0.0f;
             acc += metric == 1 ? (double)u : (double)(u * u);
         }
         S[h] = (float)acc;
@@ -525,6 +553,7 @@ int tro_features(const float *X, const float *Y, int32_t n, float tau,
     if (!X || !Y || !C || !Ghat || !F || n < 2) return -1;
     float q = tau * 0.25f, edge[16];
     for (int k = 0; k < 16; ++k) edge[k] = (float)k * q;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t a = 0; a < n; ++a) {
         int64_t deg = 0, sum = 0, hist[16] = {0};
         int32_t mx = 0;

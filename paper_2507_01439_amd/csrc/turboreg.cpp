@@ -198,6 +198,8 @@ tr_status check_params(tr_handle *h, const tr_params *p)
     if (!(p->tau >= 0.0f) || !std::isfinite(p->tau)) return TR_ERR_INVALID_ARG;
     if (!(p->inlier_thresh >= 0.0f) || !std::isfinite(p->inlier_thresh)) return TR_ERR_INVALID_ARG;
     if ((p->flags & TR_FLAG_RANK_MAE) && (p->flags & TR_FLAG_RANK_MSE)) return TR_ERR_INVALID_ARG;
+    // the error-based scores divide by theta
+    if ((p->flags & (TR_FLAG_RANK_MAE | TR_FLAG_RANK_MSE)) && !(p->inlier_thresh > 0.0f)) return TR_ERR_INVALID_ARG;
     if (p->k1 < 1 || p->k2 < 1 || p->k2 > TR_MAX_K2) return TR_ERR_INVALID_ARG;
     if (p->graph != TR_GRAPH_O2 && p->graph != TR_GRAPH_SC2) return TR_ERR_INVALID_ARG;
     if (p->pivot_mode != TR_PIVOTS_PLAIN && p->pivot_mode != TR_PIVOTS_LEARNED) return TR_ERR_INVALID_ARG;
@@ -517,6 +519,7 @@ tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32
     if (!h || !src || !dst || !poses_dev || !in_dev || n < 1 || P < 0) return TR_ERR_INVALID_ARG;
     if (!(theta >= 0.0f) || !std::isfinite(theta) || metric < 0 || metric > 2 || (metric && !score_dev))
         return TR_ERR_INVALID_ARG;
+    if (metric && !(theta > 0.0f)) return TR_ERR_INVALID_ARG;   // the error-based scores divide by theta
     if (P == 0) return TR_OK;
     if (hipSetDevice(h->device) != hipSuccess) return TR_ERR_HIP;
     const hipError_t e = launch_score_poses(src, dst, n, poses_dev, P, theta, metric, in_dev, score_dev,

@@ -533,6 +533,28 @@ def test_error_scores_hand_example():
         assert oracle.score_metric(Z, Z, pose_t, valid, 0.1, m)[0] == 7.0
 
 
+def test_error_scores_truncated_at_zero():
+    # u = max(0, (theta - e) / theta) is never negative. For a normal theta^2 the correctly
+    # rounded sqrt of fl(theta^2) is theta itself, so e <= theta for every inlier; a theta whose
+    # square is subnormal has lost bits, and a match at exactly theta is then an inlier
+    # (r^2 = fl(theta^2)) with e > theta: its u is truncated to 0. A second match with zero
+    # residual has u = 1, so both forms score exactly 1.
+    theta = np.float32(1.1 * 2.0 ** -70)
+    with np.errstate(under="ignore"):
+        th2 = np.float32(theta * theta)
+    assert 0 < th2 < np.finfo(np.float32).tiny and np.sqrt(th2) > theta   # the premise
+    X = np.array([[theta, 0, 0], [0, 0, 0]], np.float32)
+    Y = np.zeros((2, 3), np.float32)
+    pose = np.array([[1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0]], np.float32)
+    valid = np.ones(1, np.int32)
+    assert oracle.score(X, Y, pose, valid, float(theta))[0] == 2
+    assert oracle.score_metric(X, Y, pose, valid, float(theta), oracle.METRIC_MAE)[0] == 1.0
+    assert oracle.score_metric(X, Y, pose, valid, float(theta), oracle.METRIC_MSE)[0] == 1.0
+    # theta = 0 makes u = 0 / 0: the error-based rankings refuse it
+    with pytest.raises(RuntimeError):
+        oracle.score_metric(X, Y, pose, valid, 0.0, oracle.METRIC_MAE)
+
+
 def test_error_scores_order_and_bounds():
     rng = np.random.default_rng(9)
     X = rng.random((300, 3)).astype(np.float32)
@@ -588,3 +610,26 @@ def test_generator_statistics(seed):
     res = p.dst[p.labels].astype(np.float64) - (p.src[p.labels].astype(np.float64) @ p.R.T + p.t)
     assert 0.015 < res.std() < 0.025
     assert abs(np.linalg.det(p.R) - 1) < 1e-12 and np.linalg.norm(p.t) <= 1.0
+
+
+def test_openmp_build_computes_the_same_bits():
+    # the OpenMP build only splits loops with disjoint outputs: every step must agree bit for bit
+    p = small_pair(n=700, ratio=0.2, seed=5)
+    prev = oracle.set_threaded(False)
+    try:
+        C1, b1, b64, f1 = oracle.compat(p.src, p.dst, 0.1)
+        G1 = oracle.sc2(C1)
+        P1, n1 = oracle.pivots(oracle.o2graph(G1), 200)
+        cl1 = oracle.cliques(oracle.o2graph(G1), P1, n1, 200, 3)
+        r1, m1 = oracle.register(p.src, p.dst, 0.1, 0.1, 200, 2)
+        oracle.set_threaded(True)
+        C2, b2, b642, f2 = oracle.compat(p.src, p.dst, 0.1)
+        G2 = oracle.sc2(C2)
+        P2, n2 = oracle.pivots(oracle.o2graph(G2), 200)
+        cl2 = oracle.cliques(oracle.o2graph(G2), P2, n2, 200, 3)
+        r2, m2 = oracle.register(p.src, p.dst, 0.1, 0.1, 200, 2)
+    finally:
+        oracle.set_threaded(prev)
+    assert np.array_equal(C1, C2) and (b1, b64, f1) == (b2, b642, f2)
+    assert np.array_equal(G1, G2) and np.array_equal(P1, P2) and n1 == n2 and np.array_equal(cl1, cl2)
+    assert bytes(r1) == bytes(r2) and np.array_equal(m1, m2)
