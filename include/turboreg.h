@@ -243,9 +243,13 @@ enum { TR_STAGE_PLAN = 0, TR_STAGE_COMPAT, TR_STAGE_SC2, TR_STAGE_PIVOTS, TR_STA
  * other calls recorded them) since the previous read (HIP events recorded on each call's stream, kept in
  * a ring so profiled calls never wait on the host). Synchronises those events
  * and resets the averages. TR_ERR_INVALID_ARG if no profiled call was made.
- * count <= TR_NUM_STAGES. Cliques, rigid fits, scoring and selection run in
- * one kernel, timed as TR_STAGE_CLIQUES; the KABSCH, SCORE and SELECT entries
- * time back-to-back events only. */
+ * count <= TR_NUM_STAGES. Events open only stages that launch a kernel: PLAN is
+ * 0 for single-pair calls (no planner) and LEARNED is 0 with plain pivots.
+ * Clique search, rigid fits, scoring and selection run in one kernel: its event
+ * interval is split into CLIQUES (clique search), KABSCH (fits), SCORE (inlier
+ * numbers and per-item records) and SELECT (argmax, result and mask) by the
+ * shares of its workgroups' time in each phase, from in-kernel clock stamps of
+ * the profiled calls. */
 tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count);
 
 const char *tr_status_string(int32_t status);

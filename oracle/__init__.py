@@ -88,6 +88,9 @@ def _declare(L):
     L.tro_select_score.argtypes = [_f32p, I]
     L.tro_select_score.restype = I
     L.tro_register.argtypes = [_f32p, _f32p, I, ct.POINTER(Params), ct.POINTER(Result), ct.c_void_p]
+    vp = ct.c_void_p
+    L.tro_register_ex.argtypes = [_f32p, _f32p, I, ct.POINTER(Params), I, vp, vp, ct.POINTER(Result), vp,
+                                  vp, vp, vp, vp, vp, vp]
     L.tro_features.argtypes = [_f32p, _f32p, I, ct.c_float, _u8p, _i32p, _f64p]
     L.tro_mlp_fwd.argtypes = [_f64p, I] + [_f64p] * 6 + [_f64p]
     bwd = [_f64p, _u8p, I] + [_f64p] * 6 + [_f64p] * 6 + [ct.POINTER(ct.c_double)]
@@ -98,6 +101,8 @@ def _declare(L):
     L.tro_pivots_learned.argtypes = [_i32p, I, _f32p, I, _i32p]
     L.tro_bf16_round.argtypes = [ct.c_float]
     L.tro_bf16_round.restype = ct.c_float
+    L.tro_threads.argtypes = []
+    L.tro_threads.restype = I
 
 
 def _pts(a):
@@ -220,6 +225,30 @@ def register(X, Y, tau, theta, k1, k2, graph=0, threaded=None):
     return r, m
 
 
+def register_ex(X, Y, tau, theta, k1, k2, graph=0, pool_factor=0, scores=None, poses=None, threaded=None):
+    """Whole path with the learned reorder of the pool by `scores` (N float32, or None for plain
+    pivots) and scoring on the given float32 `poses` (H x 12, or None for the path's own fits
+    rounded to float32) -> (Result, mask, per-hypothesis arrays)."""
+    X, Y = _pts(X), _pts(Y)
+    n, H = X.shape[0], int(k1) * int(k2)
+    p = Params(tau, theta, k1, k2, graph)
+    r = Result()
+    m = np.empty(n, np.uint8)
+    out = dict(cliques=np.empty((H, 3), np.int32), R=np.empty((H, 3, 3)), t=np.empty((H, 3)),
+               flags=np.empty(H, np.int32), IN=np.empty(H, np.int32), pivots=np.empty((int(k1), 3), np.int32))
+    if scores is not None:
+        scores = np.ascontiguousarray(scores, np.float32)
+        assert scores.shape == (n,)
+    if poses is not None:
+        poses = np.ascontiguousarray(poses, np.float32)
+        assert poses.shape == (H, 12)
+    ptr = lambda a: None if a is None else a.ctypes.data  # noqa: E731
+    _check(lib(threaded).tro_register_ex(X, Y, n, ct.byref(p), int(pool_factor), ptr(scores), ptr(poses),
+                                         ct.byref(r), m.ctypes.data, *(ptr(out[k]) for k in
+                                         ("cliques", "R", "t", "flags", "IN", "pivots"))), "register_ex")
+    return r, m, out
+
+
 def features(X, Y, tau, C, Ghat):
     X, Y = _pts(X), _pts(Y)
     n = X.shape[0]
@@ -267,6 +296,11 @@ def pivots_learned(P_plain, s, k1):
     rc = lib().tro_pivots_learned(P_plain, P_plain.shape[0], s, int(k1), P)
     _check(rc, "pivots_learned")
     return P, bool(rc)
+
+
+def threads(threaded=None) -> int:
+    """Threads the selected build's loops use."""
+    return int(lib(threaded).tro_threads())
 
 
 def bf16_round(x):

@@ -21,6 +21,9 @@
 #include "turboreg_oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -474,12 +477,27 @@ int32_t tro_select_score(const float *S, int32_t H)
 int tro_register(const float *X, const float *Y, int32_t n, const tro_params *p,
                  tro_result *out, uint8_t *mask)
 {
+    return tro_register_ex(X, Y, n, p, 0, NULL, NULL, out, mask, NULL, NULL, NULL, NULL, NULL, NULL);
+}
+
+/* The whole path in the paper's order, optionally with the learned reorder of the pivot pool by
+ * given scores, optionally scoring given float32 poses instead of the fit's own rounding (the
+ * inlier numbers are defined on identical float32 poses), and optionally returning every
+ * hypothesis's clique, float64 fit and inlier number. */
+int tro_register_ex(const float *X, const float *Y, int32_t n, const tro_params *p, int32_t pool_factor,
+                    const float *scores, const float *poses_in, tro_result *out, uint8_t *mask,
+                    int32_t *cliques_out, double *R_out, double *t_out, int32_t *flags_out,
+                    int32_t *IN_out, int32_t *pivots_out)
+{
     if (!X || !Y || !p || !out || n < 3 || p->k1 < 1 || p->k2 < 1) return -1;
+    if (scores && pool_factor < 1) return -1;
     memset(out, 0, sizeof(*out));
     int64_t nn = (int64_t)n * n;
     int64_t H = (int64_t)p->k1 * p->k2;
+    const int32_t pool = scores ? p->k1 * pool_factor : p->k1;
     uint8_t *C = (uint8_t *)malloc((size_t)nn);
     int32_t *G = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+    int32_t *Pp = (int32_t *)malloc((size_t)pool * 3 * sizeof(int32_t));
     int32_t *P = (int32_t *)malloc((size_t)p->k1 * 3 * sizeof(int32_t));
     int32_t *cl = (int32_t *)malloc((size_t)H * 3 * sizeof(int32_t));
     double *R = (double *)malloc((size_t)H * 9 * sizeof(double));
@@ -488,14 +506,24 @@ int tro_register(const float *X, const float *Y, int32_t n, const tro_params *p,
     float *poses = (float *)malloc((size_t)H * 12 * sizeof(float));
     int32_t *IN = (int32_t *)malloc((size_t)H * sizeof(int32_t));
     int rc = -3;
-    if (!C || !G || !P || !cl || !R || !t || !flags || !poses || !IN) goto done;
+    if (!C || !G || !Pp || !P || !cl || !R || !t || !flags || !poses || !IN) goto done;
     rc = tro_compat(X, Y, n, p->tau, C, &out->n_boundary32, &out->n_boundary64, &out->n_flip);
     if (rc) goto done;
     rc = tro_sc2(C, n, G);
     if (rc) goto done;
     if (p->graph == 0) tro_o2graph(G, n, G);
-    out->n_pivots = tro_pivots(G, n, p->k1, P);
-    if (out->n_pivots < 0) { rc = (int)out->n_pivots; goto done; }
+    {
+        int64_t np = tro_pivots(G, n, pool, Pp);
+        if (np < 0) { rc = (int)np; goto done; }
+        out->n_pivots = np < p->k1 ? np : p->k1;
+    }
+    if (scores) {
+        rc = tro_pivots_learned(Pp, pool, scores, p->k1, P);
+        if (rc < 0) goto done;
+    } else {
+        memcpy(P, Pp, (size_t)p->k1 * 3 * sizeof(int32_t));
+    }
+    if (pivots_out) memcpy(pivots_out, P, (size_t)p->k1 * 3 * sizeof(int32_t));
     rc = tro_cliques(G, n, P, (int32_t)out->n_pivots, p->k1, p->k2, cl);
     if (rc) goto done;
     rc = tro_kabsch(X, Y, cl, (int32_t)H, R, t, flags);
@@ -505,6 +533,7 @@ int tro_register(const float *X, const float *Y, int32_t n, const tro_params *p,
         for (int k = 0; k < 3; ++k) poses[12 * h + 9 + k] = (float)t[3 * h + k];
         out->n_valid_hyp += flags[h] != 0;
     }
+    if (poses_in) memcpy(poses, poses_in, (size_t)H * 12 * sizeof(float));
     rc = tro_score(X, Y, n, poses, flags, (int32_t)H, p->theta, IN);
     if (rc) goto done;
     int32_t hb = tro_select(IN, (int32_t)H);
@@ -523,9 +552,14 @@ int tro_register(const float *X, const float *Y, int32_t n, const tro_params *p,
         memcpy(out->t32, poses + 12 * (int64_t)hb + 9, 3 * sizeof(float));
         if (mask) tro_mask(X, Y, n, poses + 12 * (int64_t)hb, p->theta, mask);
     }
+    if (cliques_out) memcpy(cliques_out, cl, (size_t)H * 3 * sizeof(int32_t));
+    if (R_out) memcpy(R_out, R, (size_t)H * 9 * sizeof(double));
+    if (t_out) memcpy(t_out, t, (size_t)H * 3 * sizeof(double));
+    if (flags_out) memcpy(flags_out, flags, (size_t)H * sizeof(int32_t));
+    if (IN_out) memcpy(IN_out, IN, (size_t)H * sizeof(int32_t));
     rc = 0;
 done:
-    free(C); free(G); free(P); free(cl); free(R); free(t); free(flags); free(poses); free(IN);
+    free(C); free(G); free(Pp); free(P); free(cl); free(R); free(t); free(flags); free(poses); free(IN);
     return rc;
 }
 
@@ -732,4 +766,14 @@ int tro_pivots_learned(const int32_t *P_plain, int32_t pool, const float *s, int
     }
     free(k);
     return fallback;
+}
+
+/* Threads the OpenMP loops above use (1 in the build without OpenMP). */
+int tro_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

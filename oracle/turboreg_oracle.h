@@ -92,6 +92,16 @@ typedef struct {
  * 3 = no valid hypothesis (R = I, t = 0). mask may be NULL. */
 int tro_register(const float *X, const float *Y, int32_t n, const tro_params *p,
                  tro_result *out, uint8_t *mask);
+/* The same path with three options. scores (nullable, N float32): select the first
+ * pool_factor*k1 plain pivots and reorder them by the learned keys (tro_pivots_learned) before
+ * the cliques. poses_in (nullable, H x 12 float32): score and select on these poses instead of
+ * the float32 rounding of the path's own fits (inlier numbers are defined on identical float32
+ * poses). The nullable outputs receive every hypothesis's clique (H x 3), float64 fit
+ * (H x 9, H x 3), fit flag (H), inlier number (H) and the pivots used (k1 x 3). */
+int tro_register_ex(const float *X, const float *Y, int32_t n, const tro_params *p, int32_t pool_factor,
+                    const float *scores, const float *poses_in, tro_result *out, uint8_t *mask,
+                    int32_t *cliques_out, double *R_out, double *t_out, int32_t *flags_out,
+                    int32_t *IN_out, int32_t *pivots_out);
 
 /* ---- learned pivot scorer (float64 reference) ---- */
 
@@ -137,6 +147,9 @@ int tro_pivots_learned(const int32_t *P_plain, int32_t pool, const float *s, int
 
 /* float -> bfloat16 -> float, round to nearest even (NaN kept NaN). */
 float tro_bf16_round(float x);
+
+/* Threads the parallel loops use: omp_get_max_threads() in the OpenMP build, else 1. */
+int tro_threads(void);
 
 #ifdef __cplusplus
 }

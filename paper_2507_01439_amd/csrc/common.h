@@ -69,7 +69,9 @@ struct Work {
     int32_t graph;
     int32_t sc2_super;        // SC2 tile walk: super-tile side in output tiles (launch configuration)
     float tau, theta;
-    uint8_t *C;               // C arena
+    uint8_t *C;               // C arena (E2M1 nibbles, the MFMA operands)
+    uint8_t *Cbits;           // C arena as bits: per pair npad x npad bits in blocks of 128 columns,
+                              // [column / 128][row][16 bytes] (bit c % 8 of byte (c % 128) / 8); offset c_off / 8
     uint16_t *G;              // G arena
     int32_t *ghist;           // max_batch x kHistGroups x hist_stride weight histograms (filled by the SC2 epilogue)
     int32_t hist_stride;      // max_n rounded up to 8 (16-byte aligned copies)
@@ -105,7 +107,15 @@ struct Work {
     tr_result *out;
     uint8_t *masks;           // nullable; pair b's mask starts at pairs[b].pt_off
     int32_t learned;          // learned pivot mode / feature accumulation on
+    // Profiled calls only (null otherwise): the hypothesis kernel's phase durations in ticks of
+    // the 100 MHz real-time clock, per work item (max_batch x rec_stride / 2 x 4: clique search,
+    // rigid fits, scoring, records), and their sums over calls (kProfSlots counters).
+    uint32_t *hyp_prof;
+    unsigned long long *prof_acc;
 };
+
+// Sums of the hypothesis kernel's phases over profiled calls (prof_acc slots).
+enum { kProfSearch = 0, kProfFit, kProfScore, kProfRecords, kProfSelect, kProfItems, kProfPairs, kProfSlots };
 
 
 // Largest b in [0, B) with pre[b] <= item (pre is non-decreasing, pre[0] = 0).

@@ -166,6 +166,15 @@ __device__ __forceinline__ uint32_t pack_e2m1(uint32_t x)
     return ((x << 1) & 0x2u) | ((x >> 3) & 0x20u) | ((x >> 7) & 0x200u) | ((x >> 11) & 0x2000u);
 }
 
+// Eight E2M1 entries (0x2 = 1, 0x0 = 0) of a packed word -> eight bits, entry k -> bit k.
+__device__ __forceinline__ uint32_t nibbles_to_bits(uint32_t x)
+{
+    x = (x >> 1) & 0x11111111u;          // entry k at bit 4k
+    x = (x | (x >> 3)) & 0x03030303u;    // entries 2m, 2m+1 at bits 8m, 8m+1
+    x = (x | (x >> 6)) & 0x000F000Fu;    // at bits 16m .. 16m+3
+    return (x | (x >> 12)) & 0xFFu;
+}
+
 // Guard band of the fast compatibility test: v_sqrt_f32 is within a few ulps,
 // so |delta_fast - delta_exact| <= 2^-21 (|x| + |y|); a pair whose fast delta
 // lies within 2^-19 (|x| + |y|) + 2e-6 of tau is re-evaluated exactly, which
@@ -363,6 +372,21 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         if (!diag)
             *reinterpret_cast<uint2 *>(Cb + ((int64_t)bj * kCompatTile + r) * rs + bi * (kCompatTile / 2) + c8) =
                 *reinterpret_cast<const uint2 *>(&tile[1][r * kNibStride + c8]);
+        if (tid < (diag ? 64 : 128)) {
+            // the same rows as bits (threads 0-63: the tile's rows, 64-127: its transpose), 8 bytes per
+            // row into the 16-byte piece of the row's 128-column block
+            const int side = tid >> 6, rr = tid & 63;
+            const uint4 *src = reinterpret_cast<const uint4 *>(&tile[side][rr * kNibStride]);
+            const uint4 lo = src[0], hi = src[1];
+            const uint32_t nib[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            uint32_t word[2] = {0, 0};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) word[k >> 2] |= nibbles_to_bits(nib[k]) << (8 * (k & 3));
+            const int rb = side ? bj : bi, cb = side ? bi : bj;
+            uint8_t *dst = w.Cbits + d.c_off / 8 +
+                           ((int64_t)(cb >> 1) * d.npad + (int64_t)rb * kCompatTile + rr) * 16 + (cb & 1) * 8;
+            *reinterpret_cast<uint2 *>(dst) = make_uint2(word[0], word[1]);
+        }
         if (tid < 3) w.cnt_part[3 * (int64_t)item + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
         if (LEARNED) {
             for (int k = tid; k < 64 * 17; k += 256) {
@@ -397,6 +421,18 @@ constexpr int kHistLdsBins = 8192;             // weights below this are histogr
 constexpr int kSc2Lds = kRingBytes + kHistLdsBins * 4;   // 160 KiB: ring (then tile), histogram
 static_assert(kTileBytes <= kRingBytes, "the finished tile must fit the ring");
 constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then the low 16 bits of 2^23 + v
+// Bit-count path (tiles with few edges): Eq. 2 is needed only where C_ij = 1, so a tile holding at
+// most kSddmmCap edges counts popcount(row_i AND row_j) for each of its edges instead of forming
+// the dense product. Rows arrive in chunks of kChunkKb 128-column blocks (bits); LDS layout:
+// two chunk buffers (I rows then J rows, [block][row][16 bytes] each), the edge list, the counts.
+constexpr int kSddmmCap = 8192;                       // 32 edges per thread
+constexpr int kChunkKb = 4;                           // 512 columns of C per chunk
+constexpr int kChunkSide = kChunkKb * kSc2Tile * 16;  // 16 KiB: one side's 256 rows of a chunk
+constexpr int kChunkBytes = 2 * kChunkSide;
+constexpr int kEdgeOff = 2 * kChunkBytes;             // edge list: uint16 (i_local << 8 | j_local)
+constexpr int kCntOff = kEdgeOff + 2 * kSddmmCap;     // counts: int32 per edge
+constexpr int kScanOff = kCntOff + 4 * kSddmmCap;     // four wave totals of the edge-count scan
+static_assert(kScanOff + 64 <= kRingBytes, "the bit-count path stays below the histogram");
 
 // Wait until at most N vector-memory loads of this wave are outstanding, then
 // meet the other waves. The memory clobber keeps LDS reads of the new stage
@@ -474,6 +510,133 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         const uint8_t *Cb = w.C + d.c_off / 2;
         const int64_t rs = d.npad / 2;       // packed row bytes
         const int nk = (int)(rs / kBK);
+        // ---- the tile's edges: thread t holds row t of the I block over the tile's 256 columns
+        const uint8_t *Cbit = w.Cbits + d.c_off / 8;
+        const int64_t kbs = (int64_t)d.npad * 16;   // bytes of one 128-column block over all rows
+        const bool diag = bi == bj;
+        uint32_t mw[8];
+        {
+            const int64_t ro = ((int64_t)bi * kSc2Tile + tid) * 16;
+            const uint4 m0 = *reinterpret_cast<const uint4 *>(Cbit + (2 * bj) * kbs + ro);
+            const uint4 m1 = *reinterpret_cast<const uint4 *>(Cbit + (2 * bj + 1) * kbs + ro);
+            mw[0] = m0.x; mw[1] = m0.y; mw[2] = m0.z; mw[3] = m0.w;
+            mw[4] = m1.x; mw[5] = m1.y; mw[6] = m1.z; mw[7] = m1.w;
+        }
+        int ecount = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (diag) {   // i < j only: columns above the thread's row
+                const int lo = tid + 1 - 32 * k;
+                mw[k] &= lo <= 0 ? 0xFFFFFFFFu : (lo >= 32 ? 0u : (0xFFFFFFFFu << lo));
+            }
+            ecount += __builtin_popcount(mw[k]);
+        }
+        int32_t *scanL = reinterpret_cast<int32_t *>(smem + kScanOff);
+        int eprefix = ecount;   // inclusive scan inside the wave, then the waves before
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(eprefix, o, 64);
+            if (lane >= o) eprefix += y;
+        }
+        if (lane == 63) scanL[wv] = eprefix;
+        __syncthreads();
+        const int etotal = scanL[0] + scanL[1] + scanL[2] + scanL[3];
+        for (int v = 0; v < wv; ++v) eprefix += scanL[v];
+        eprefix -= ecount;   // exclusive
+        const bool sparse = etotal <= kSddmmCap;
+        if (sparse) {
+            uint16_t *edgeL = reinterpret_cast<uint16_t *>(smem + kEdgeOff);
+            int32_t *cntL = reinterpret_cast<int32_t *>(smem + kCntOff);
+            {
+                int pos = eprefix;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    uint32_t x = mw[k];
+                    while (x) {
+                        const int c = __builtin_ctz(x);
+                        x &= x - 1;
+                        edgeL[pos] = (uint16_t)((tid << 8) | (32 * k + c));
+                        cntL[pos] = 0;
+                        ++pos;
+                    }
+                }
+            }
+            __syncthreads();   // the edge list is complete
+            // thread t counts edges [e0, e1): about etotal / 256 consecutive edges (few rows each)
+            const int q = (etotal + 255) >> 8, e0 = min(etotal, tid * q), e1 = min(etotal, e0 + q);
+            const int nkb = d.npad / 128, nch = (nkb + kChunkKb - 1) / kChunkKb;
+            // chunk c: blocks 4c.. of the I rows (and J rows off the diagonal) by direct
+            // global->LDS 16-byte loads; wave v loads rows 64v .. 64v+63 of each block
+            auto issue_chunk = [&](int c) {
+                uint8_t *dst = smem + (c & 1) * kChunkBytes + wv * 1024;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (side && diag) break;
+                    const int64_t ro = ((int64_t)(side ? bj : bi) * kSc2Tile + wv * 64 + lane) * 16;
+#pragma unroll
+                    for (int kb = 0; kb < kChunkKb; ++kb)
+                        if (c * kChunkKb + kb < nkb)
+                            __builtin_amdgcn_global_load_lds((gvoid *)(Cbit + (int64_t)(c * kChunkKb + kb) * kbs + ro),
+                                                             (lvoid *)(dst + side * kChunkSide + kb * 4096), 16, 0, 0);
+                }
+            };
+            if (etotal > 0) issue_chunk(0);
+            for (int c = 0; c < (etotal > 0 ? nch : 0); ++c) {
+                SC2_WAIT_BARRIER(0);   // chunk c has landed for every wave (and the edge list is written)
+                if (c + 1 < nch) issue_chunk(c + 1);
+                const uint8_t *Ib = smem + (c & 1) * kChunkBytes, *Jb = diag ? Ib : Ib + kChunkSide;
+                const int kbn = min(kChunkKb, nkb - c * kChunkKb);
+                int cur = -1;
+                uint4 ri[kChunkKb];
+                for (int e = e0; e < e1; ++e) {
+                    const uint32_t v = edgeL[e];
+                    const int li = v >> 8, lj = v & 255;
+                    if (li != cur) {
+                        cur = li;
+#pragma unroll
+                        for (int kb = 0; kb < kChunkKb; ++kb)
+                            if (kb < kbn) ri[kb] = *reinterpret_cast<const uint4 *>(Ib + kb * 4096 + li * 16);
+                    }
+                    int sum = 0;
+#pragma unroll
+                    for (int kb = 0; kb < kChunkKb; ++kb) {
+                        if (kb < kbn) {
+                            const uint4 rj = *reinterpret_cast<const uint4 *>(Jb + kb * 4096 + lj * 16);
+                            sum += __builtin_popcount(ri[kb].x & rj.x) + __builtin_popcount(ri[kb].y & rj.y) +
+                                   __builtin_popcount(ri[kb].z & rj.z) + __builtin_popcount(ri[kb].w & rj.w);
+                        }
+                    }
+                    cntL[e] += sum;
+                }
+                __syncthreads();   // this buffer is read for the last time before chunk c + 2 lands in it
+            }
+            // this thread's edges and counts to registers; the LDS becomes the tile T (zero, then
+            // the counts scattered in; weights below 2^16)
+            uint32_t myv[32];
+            int myc[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                myv[k] = e0 + k < e1 ? edgeL[e0 + k] : 0u;
+                myc[k] = e0 + k < e1 ? cntL[e0 + k] : 0;
+            }
+            __syncthreads();
+            for (int k = tid; k < kTileBytes / 16; k += 256) reinterpret_cast<uint4 *>(smem)[k] = make_uint4(0, 0, 0, 0);
+            __syncthreads();
+            int32_t *ghs = w.ghist + ((int64_t)b * kHistGroups + local % kHistGroups) * w.hist_stride;
+            const bool small_hist = d.n <= kHistLdsBins;
+#pragma unroll
+            for (int k = 0; k < 32; ++k) {
+                if (e0 + k < e1) {
+                    T[(myv[k] >> 8) * kSc2Tile + (myv[k] & 255)] = (uint16_t)myc[k];
+                    const int c = myc[k];
+                    if (c > 0) {   // the weight histogram counts nonzero weights
+                        if (small_hist || c < kHistLdsBins) atomicAdd(&hist[c], 1);
+                        else atomicAdd(&ghs[c], 1);
+                    }
+                }
+            }
+            __syncthreads();
+        } else {
         // load s of a stage: row r = (s&3)*64 + wv*16 + lane/4 of operand s/4 into LDS chunk lane&3,
         // which holds the row's global chunk (lane&3) ^ ((r/4)&3)
         uint32_t goff[8];
@@ -559,6 +722,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 }
             }
         __syncthreads();
+        }   // dense (MFMA) path
         int32_t *gh = w.ghist + ((int64_t)b * kHistGroups + local % kHistGroups) * w.hist_stride;
         int32_t *rowmax = w.rowmax + (int64_t)b * w.max_n;
         int32_t *rstat = w.rowstat + (int64_t)b * w.max_n * 20;
@@ -572,15 +736,18 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         const int cc = tid & 31;
         const int j0 = bj * kSc2Tile + cc * 8;
         const uint8_t *crow = Cb + ((int64_t)bi * kSc2Tile + (tid >> 5)) * rs + j0 / 2;
+        // (the bit-count path's T holds only its edges' weights: no C_ij or range masking)
         uint32_t cur[8], nxt[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) cur[q] = *reinterpret_cast<const uint32_t *>(crow + (int64_t)(q * 8) * rs);
+        for (int q = 0; q < 8; ++q)
+            cur[q] = sparse ? 0x22222222u : *reinterpret_cast<const uint32_t *>(crow + (int64_t)(q * 8) * rs);
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb) {
             if (kb < 3) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q)
-                    nxt[q] = *reinterpret_cast<const uint32_t *>(crow + (int64_t)(((kb + 1) * 8 + q) * 8) * rs);
+                    nxt[q] = sparse ? 0x22222222u
+                                    : *reinterpret_cast<const uint32_t *>(crow + (int64_t)(((kb + 1) * 8 + q) * 8) * rs);
             }
             uint4 tv[8];
 #pragma unroll
@@ -597,7 +764,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 const uint32_t tw[4] = {tv[q].x, tv[q].y, tv[q].z, tv[q].w};
                 // entries e of the chunk with i < j0 + e < n (all eight except at the diagonal and the edge)
                 const int e_lo = min(8, max(0, i + 1 - j0)), e_hi = min(8, max(0, d.n - j0));
-                const uint32_t vm = interior ? 0xFFu : (((1u << e_hi) - 1u) & ~((1u << e_lo) - 1u));
+                const uint32_t vm = (interior || sparse) ? 0xFFu : (((1u << e_hi) - 1u) & ~((1u << e_lo) - 1u));
                 const uint32_t cb = cur[q] >> 1;   // C of column e at bit 4e
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -632,6 +799,7 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
             // lane-varying switch would become branches).
 #pragma unroll
             for (int g4 = 0; g4 < 2; ++g4) {
+                if (sparse) break;   // the bit-count path histogrammed its edges already
                 uint32_t nz = 0;
                 uint64_t h64[8];
 #pragma unroll

@@ -403,6 +403,7 @@ __device__ void select_pair(const Work &w, int b, int ipp)
     __shared__ uint64_t red_k[NW];
     __shared__ int32_t red_n[NW];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint64_t t_sel0 = w.hyp_prof ? __builtin_amdgcn_s_memrealtime() : 0;
     const PairDesc d = pair_desc(w, b);
     // the mask's first matches (kM per thread) do not depend on the selection: their loads are
     // issued before the records are read
@@ -505,6 +506,34 @@ __device__ void select_pair(const Work &w, int b, int ipp)
             }
         }
     }
+    if (w.hyp_prof) {
+        // profiled call: this pair's phase durations, summed over its items (written before their
+        // tickets), and the selection's own duration, added to the per-handle sums
+        __syncthreads();
+        const uint32_t *ip = w.hyp_prof + (int64_t)b * w.rec_stride * 2;
+        unsigned long long sum[4] = {0, 0, 0, 0};
+        for (int k = tid; k < ipp; k += NT)
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                sum[f] += __hip_atomic_load(ip + 4 * k + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            sum[f] = (unsigned long long)wave_total((int)sum[f]);
+            if (lane == 0) red_k[wv] = sum[f];
+            __syncthreads();
+            if (tid == 0) {
+                unsigned long long t = 0;
+                for (int v = 0; v < NW; ++v) t += red_k[v];
+                atomicAdd(&w.prof_acc[kProfSearch + f], t);
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            atomicAdd(&w.prof_acc[kProfSelect], (unsigned long long)(__builtin_amdgcn_s_memrealtime() - t_sel0));
+            atomicAdd(&w.prof_acc[kProfItems], (unsigned long long)ipp);
+            atomicAdd(&w.prof_acc[kProfPairs], 1ull);
+        }
+    }
 }
 
 // One DPP move of a float (the control word is a template constant).
@@ -560,12 +589,17 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
         const int b = item / ipp, g = item - b * ipp;
         const PairDesc d = pair_desc(w, b);
         const int nloc = ppw * w.k2;   // local hypothesis hl = (pivot lp) * K2 + slot
+        // profiled calls: phase stamps of thread 0 (clique search of wave 0's pivots, fits up to
+        // the workgroup barrier, scoring, records), 100 MHz real-time clock
+        uint64_t ts0 = 0, ts1 = 0, ts2 = 0, ts3 = 0;
+        if (w.hyp_prof) ts0 = ts1 = __builtin_amdgcn_s_memrealtime();
         if (tid < 16 * TR_MAX_K2) tot_l[tid] = 0;
         for (int r = 0; r < (ppw + NW - 1) / NW; ++r) {
             const int lp = r * NW + wv, p = g * ppw + lp;
             if (lp >= ppw) break;   // the same on the whole wave
             int pi = -1, pj = -1, z = -1;
             if (p < w.k1) z = clique_search<KMAX>(w, d, b, p, lane, pi, pj);
+            if (w.hyp_prof && tid == 0) ts1 = __builtin_amdgcn_s_memrealtime();
             if (lane < w.k2) {
                 float pose[12];
                 const bool ok = p < w.k1 && fit_pose(w, d, pi, pj, z, pose);
@@ -576,6 +610,7 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
             }
         }
         __syncthreads();
+        if (w.hyp_prof) ts2 = __builtin_amdgcn_s_memrealtime();
         for (int h0 = 0; h0 < nloc; h0 += 8) {
             float ps[8][12];
 #pragma unroll
@@ -637,6 +672,7 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
             }
         }
         __syncthreads();
+        if (w.hyp_prof) ts3 = __builtin_amdgcn_s_memrealtime();
         uint64_t key = 0;
         int nv = 0;
         if (tid < nloc) {
@@ -678,6 +714,14 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
             uint64_t *rec = w.hyp_rec + (int64_t)b * w.rec_stride + 2 * g;
             __hip_atomic_store(rec, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(rec + 1, (uint64_t)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (w.hyp_prof) {
+                const uint64_t ts4 = __builtin_amdgcn_s_memrealtime();
+                uint32_t *ip = w.hyp_prof + ((int64_t)b * w.rec_stride / 2 + g) * 4;
+                const uint32_t dur[4] = {(uint32_t)(ts1 - ts0), (uint32_t)(ts2 - ts1), (uint32_t)(ts3 - ts2),
+                                         (uint32_t)(ts4 - ts3)};
+#pragma unroll
+                for (int f = 0; f < 4; ++f) __hip_atomic_store(ip + f, dur[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         // every store of this item has been acknowledged before its ticket. Two levels of tickets:
         // the last item of a group of kHypGroup takes a ticket of the pair, and the workgroup

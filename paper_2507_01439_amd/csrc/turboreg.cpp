@@ -43,7 +43,7 @@ struct tr_handle {
     PairState *state = nullptr;
     Plan *plan = nullptr;
     int32_t *pre = nullptr;
-    uint8_t *C = nullptr;
+    uint8_t *C = nullptr, *Cbits = nullptr;
     uint16_t *G = nullptr;
     int32_t *ghist = nullptr, *rowmax = nullptr, *cnt_part = nullptr, *rowcnt = nullptr, *blkcnt = nullptr;
     uint64_t *cand = nullptr, *rowseg = nullptr, *hyp_rec = nullptr;
@@ -55,6 +55,8 @@ struct tr_handle {
     uint16_t *feat = nullptr;
     float *scores = nullptr;
     tr_result *scratch_out = nullptr;   // results of feature-only passes
+    uint32_t *hyp_prof = nullptr;       // profiled calls: per-item phase durations of the hypothesis kernel
+    unsigned long long *prof_acc = nullptr;   // and their sums (kProfSlots)
     // learned scorer
     MlpState mlp;
     bool has_scorer = false;
@@ -68,6 +70,7 @@ struct tr_handle {
     static constexpr int kRing = 256;
     std::vector<hipEvent_t> ring;          // kRing x (TR_NUM_STAGES + 1)
     std::vector<char> ring_pending;        // 0 free, 1 all stages recorded, 2 only the SC2 stage
+    std::vector<uint32_t> ring_mask;       // bit k: event k of the set was recorded (a stage with a kernel)
     int64_t ring_next = 0;
     double stage_sum[TR_NUM_STAGES] = {};
     int64_t stage_calls[TR_NUM_STAGES] = {};
@@ -104,6 +107,64 @@ void release(tr_handle *h)
     mlp_release(&h->mlp);
     for (void *p : h->allocs) hipFree(p);
     h->allocs.clear();
+}
+
+// Strides and capacities of a workspace for up to max_batch pairs of up to max_n matches,
+// K1 <= max_k1 and K2 <= max_k2.
+void size_handle(tr_handle *h, int32_t max_n, int32_t max_batch, int32_t max_k1, int32_t max_k2)
+{
+    h->max_n = max_n;
+    h->max_batch = max_batch;
+    h->max_k1 = max_k1;
+    h->max_k2 = max_k2;
+    h->npad_max = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
+    h->pool_cap = std::min(TR_MAX_POOL, 8 * max_k1);
+    h->k1_cap = max_k1;
+    h->h_cap = max_k1 * max_k2;
+    h->nblk_stride = (max_n + kRowsPerItem - 1) / kRowsPerItem;
+    const int items = (max_k1 + 3) / 4;   // clique-search work items of a pair (at least 4 pivots each)
+    h->rec_stride = 2 * items;
+    h->tick_stride = (kCollectRegions + (items + kHypGroup - 1) / kHypGroup) * kTickLine;
+    h->pre_stride = max_batch + 1;
+}
+
+// The workspace buffers of a sized handle, in order: get(pointer member, element count) places
+// each one (device allocations for a handle, a carve of the static scratch for the entry point
+// that allocates nothing).
+template <class Get>
+void workspace_layout(tr_handle *h, Get &&get)
+{
+    const size_t B = h->max_batch, nn = (size_t)h->npad_max * h->npad_max, max_n = h->max_n;
+    get(h->pairs, B);
+    get(h->state, B);
+    get(h->plan, 1);
+    get(h->pre, (size_t)kNumPrefix * h->pre_stride);
+    get(h->C, B * nn / 2);   // packed E2M1, two entries per byte
+    get(h->Cbits, B * nn / 8);   // the same matrix as bits
+    get(h->G, B * nn);
+    get(h->ghist, B * kHistGroups * (size_t)((max_n + 7) & ~(size_t)7));
+    get(h->rowmax, B * max_n);
+    const size_t nb64 = h->npad_max / kCompatTile;
+    get(h->cnt_part, B * nb64 * (nb64 + 1) / 2 * 3);   // boundary pairs, edges, non-finite flag
+    get(h->rowcnt, B * max_n);
+    get(h->blkcnt, B * h->nblk_stride);
+    get(h->cand, B * kCollectRegions * h->pool_cap);
+    get(h->tick, B * h->tick_stride);
+    get(h->hyp_rec, B * h->rec_stride);
+    get(h->rowseg, B * max_n);
+    get(h->pivots_plain, B * h->pool_cap * 3);
+    get(h->pivots, B * h->k1_cap * 3);
+    get(h->cliques, B * h->h_cap * 3);
+    get(h->poses, B * h->h_cap * 12);
+    get(h->inl, B * h->h_cap);
+    get(h->gscore, B * h->h_cap);
+    get(h->rowstat, B * max_n * 20);
+    get(h->mark, B * max_n);
+    get(h->feat, B * max_n * 19);
+    get(h->scores, B * max_n);
+    get(h->scratch_out, B);
+    get(h->hyp_prof, B * (size_t)h->rec_stride * 2);
+    get(h->prof_acc, (size_t)kProfSlots);
 }
 
 std::pair<int32_t, int32_t> tuning_key(int32_t max_n, int32_t B)
@@ -157,6 +218,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.tau = p.tau;
     w.theta = p.inlier_thresh;
     w.C = h->C;
+    w.Cbits = h->Cbits;
     w.G = h->G;
     w.ghist = h->ghist;
     w.hist_stride = (h->max_n + 7) & ~7;
@@ -216,22 +278,33 @@ tr_status check_params(tr_handle *h, const tr_params *p)
 // features_only stops after the learned features.
 tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_t n_single, int32_t B,
                   int32_t max_n, hipEvent_t *ev, int ev_mode, bool features_only, hipStream_t s,
-                  const tr_tuning &cfg)
+                  const tr_tuning &cfg, uint32_t *ev_mask = nullptr)
 {
+    uint32_t ev_mask_unused = 0;
+    if (!ev_mask) ev_mask = &ev_mask_unused;
     Work w = w_in;
     w.sc2_super = cfg.sc2_super;
     const bool profile = ev != nullptr;
     const int64_t npad = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
     const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
     const int64_t rows_items = (int64_t)B * ((max_n + kRowsPerItem - 1) / kRowsPerItem);
+    // an event opens each stage that launches a kernel (and one closes the last); a stage without
+    // a kernel records nothing, so no interval is an empty pair of events
     auto mark = [&](int stage) {
-        if (profile && (ev_mode == 1 || stage == TR_STAGE_SC2 || stage == TR_STAGE_SC2 + 1)) hipEventRecord(ev[stage], s);
+        if (profile && (ev_mode == 1 || stage == TR_STAGE_SC2 || stage == TR_STAGE_SC2 + 1)) {
+            hipEventRecord(ev[stage], s);
+            *ev_mask |= 1u << stage;
+        }
     };
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
         if (x != hipSuccess && e == hipSuccess) e = x;
     };
-    mark(TR_STAGE_PLAN);
+    if (profile && ev_mode == 1) {   // the hypothesis kernel adds its phase durations to the handle's sums
+        w.hyp_prof = h->hyp_prof;
+        w.prof_acc = h->prof_acc;
+    }
+    if (!w.n1 || (w.learned && w.feat_all)) mark(TR_STAGE_PLAN);
     if (!w.n1) chk(launch_plan(w, offsets, n_single, B, max_n, h->pairs, h->state, h->plan, h->pre, s));
     if (w.learned && w.feat_all)
         chk(launch_prep_learned(w, grid_cap(h, (int64_t)B * ((max_n + kPrepRows - 1) / kPrepRows), 8), s));
@@ -249,7 +322,7 @@ tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_
     if (features_only) return e == hipSuccess ? TR_OK : TR_ERR_HIP;
     mark(TR_STAGE_PIVOTS);
     chk(launch_pivots(w, B, grid_cap(h, rows_items, 8), s));
-    mark(TR_STAGE_LEARNED);
+    if (w.learned) mark(TR_STAGE_LEARNED);
     if (w.learned) {
         // features and scores of the pool's endpoints, then the reorder of the pool
         chk(launch_learned_order(w, h->mlp, B, h->num_cus, s));
@@ -257,9 +330,6 @@ tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_
     mark(TR_STAGE_CLIQUES);
     // cliques, their poses, their inlier counts and (last workgroup per pair) the selection
     chk(launch_hyp(w, B, cfg.hyp_ppw, h->num_cus * cfg.hyp_per_cu, s));
-    mark(TR_STAGE_KABSCH);
-    mark(TR_STAGE_SCORE);
-    mark(TR_STAGE_SELECT);
     mark(TR_NUM_STAGES);
     if (e != hipSuccess) {
         std::fprintf(stderr, "turboreg: launch failed: %s\n", hipGetErrorString(e));
@@ -283,10 +353,15 @@ hipError_t ring_collect(tr_handle *h, int slot)
     const bool all = h->ring_pending[slot] == 1;
     hipError_t e = hipEventSynchronize(ev[all ? TR_NUM_STAGES : TR_STAGE_SC2 + 1]);
     if (e != hipSuccess) return e;
+    // a recorded event opens its stage, which ends at the next recorded event; the cliques
+    // interval is the whole hypothesis kernel (split into its phases in tr_stage_times)
+    const uint32_t m = h->ring_mask[slot];
     for (int k = 0; k < TR_NUM_STAGES; ++k) {
-        if (!all && k != TR_STAGE_SC2) continue;
+        if (!(m & (1u << k)) || (!all && k != TR_STAGE_SC2)) continue;
+        int nx = k + 1;
+        while (nx < TR_NUM_STAGES && !(m & (1u << nx))) ++nx;
         float t = 0;
-        e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+        e = hipEventElapsedTime(&t, ev[k], ev[nx]);
         if (e != hipSuccess) return e;
         h->stage_sum[k] += t;
         h->stage_calls[k] += 1;
@@ -302,17 +377,20 @@ int profile_mode(uint32_t flags)
 
 // Event set for the next profiled call (created on first use); mode 1: every
 // stage, 2: the SC2 stage only.
-hipEvent_t *ring_slot(tr_handle *h, int mode)
+hipEvent_t *ring_slot(tr_handle *h, int mode, uint32_t **mask)
 {
     if (h->ring.empty()) {
         h->ring.assign((size_t)tr_handle::kRing * (TR_NUM_STAGES + 1), nullptr);
         h->ring_pending.assign(tr_handle::kRing, 0);
+        h->ring_mask.assign(tr_handle::kRing, 0);
         for (auto &e : h->ring)
             if (hipEventCreate(&e) != hipSuccess) return nullptr;
     }
     const int slot = (int)(h->ring_next % tr_handle::kRing);
     if (h->ring_pending[slot] && ring_collect(h, slot) != hipSuccess) return nullptr;
     h->ring_pending[slot] = (char)mode;
+    h->ring_mask[slot] = 0;
+    *mask = &h->ring_mask[slot];
     h->ring_next += 1;
     return &h->ring[(size_t)slot * (TR_NUM_STAGES + 1)];
 }
@@ -353,55 +431,13 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     h->device = device;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
-    h->max_n = max_n;
-    h->max_batch = max_batch;
-    h->max_k1 = max_k1;
-    h->max_k2 = max_k2;
-    h->npad_max = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
-    h->pool_cap = std::min(TR_MAX_POOL, 8 * max_k1);
-    h->k1_cap = max_k1;
-    h->h_cap = max_k1 * max_k2;
-    h->nblk_stride = (max_n + kRowsPerItem - 1) / kRowsPerItem;
-    {
-        const int items = (max_k1 + 3) / 4;   // clique-search work items of a pair (at least 4 pivots each)
-        h->rec_stride = 2 * items;
-        h->tick_stride = (kCollectRegions + (items + kHypGroup - 1) / kHypGroup) * kTickLine;
-    }
-    h->pre_stride = max_batch + 1;
-    const size_t B = max_batch, nn = (size_t)h->npad_max * h->npad_max;
+    size_handle(h, max_n, max_batch, max_k1, max_k2);
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
-    A(alloc(h, &h->pairs, B));
-    A(alloc(h, &h->state, B));
-    A(alloc(h, &h->plan, 1));
-    A(alloc(h, &h->pre, (size_t)kNumPrefix * h->pre_stride));
-    A(alloc(h, &h->C, B * nn / 2));   // packed E2M1, two entries per byte
-    A(alloc(h, &h->G, B * nn));
-    A(alloc(h, &h->ghist, B * kHistGroups * (size_t)((max_n + 7) & ~7)));
-    A(alloc(h, &h->rowmax, B * max_n));
-    {
-        const size_t nb64 = h->npad_max / kCompatTile;
-        A(alloc(h, &h->cnt_part, B * nb64 * (nb64 + 1) / 2 * 3));   // boundary pairs, edges, non-finite flag
-    }
-    A(alloc(h, &h->rowcnt, B * max_n));
-    A(alloc(h, &h->blkcnt, B * h->nblk_stride));
-    A(alloc(h, &h->cand, B * kCollectRegions * h->pool_cap));
-    A(alloc(h, &h->tick, B * h->tick_stride));
-    A(alloc(h, &h->hyp_rec, B * h->rec_stride));
-    A(alloc(h, &h->rowseg, B * max_n));
-    A(alloc(h, &h->pivots_plain, B * h->pool_cap * 3));
-    A(alloc(h, &h->pivots, B * h->k1_cap * 3));
-    A(alloc(h, &h->cliques, B * h->h_cap * 3));
-    A(alloc(h, &h->poses, B * h->h_cap * 12));
-    A(alloc(h, &h->inl, B * h->h_cap));
-    A(alloc(h, &h->gscore, B * h->h_cap));
-    A(alloc(h, &h->rowstat, B * max_n * 20));
-    A(alloc(h, &h->mark, B * max_n));
-    A(alloc(h, &h->feat, B * max_n * 19));
-    A(alloc(h, &h->scores, B * max_n));
-    A(alloc(h, &h->scratch_out, B));
+    workspace_layout(h, [&](auto *&p, size_t count) { A(alloc(h, &p, count)); });
+    if (e == hipSuccess) A(hipMemset(h->prof_acc, 0, kProfSlots * sizeof(unsigned long long)));
     if (e == hipSuccess) A(mlp_create(&h->mlp));
     A(setup_graph_kernels());
     A(setup_pivot_kernels());
@@ -441,8 +477,9 @@ tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t 
     w.n1 = n;   // the kernels derive this pair's plan from n (no planner launch)
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t *ev = nullptr;
-    if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
-    st = enqueue(h, w, nullptr, n, 1, n, ev, pmode, false, s, tuning_for(h, n, 1));
+    uint32_t *ev_mask = nullptr;
+    if (pmode && !(ev = ring_slot(h, pmode, &ev_mask))) return TR_ERR_HIP;
+    st = enqueue(h, w, nullptr, n, 1, n, ev, pmode, false, s, tuning_for(h, n, 1), ev_mask);
     if (st == TR_OK) remember(h, w, 1, s);
     return st;
 }
@@ -463,8 +500,9 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     if (pmode || s == nullptr) {
         // events (and the legacy default stream) stay out of captured graphs: run eagerly
         hipEvent_t *ev = nullptr;
-        if (pmode && !(ev = ring_slot(h, pmode))) return TR_ERR_HIP;
-        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, pmode, false, s, cfg);
+        uint32_t *ev_mask = nullptr;
+        if (pmode && !(ev = ring_slot(h, pmode, &ev_mask))) return TR_ERR_HIP;
+        st = enqueue(h, w, offsets_dev, 0, B, max_n, ev, pmode, false, s, cfg, ev_mask);
         if (st == TR_OK) remember(h, w, B, s);
         return st;
     }
@@ -712,8 +750,25 @@ tr_status tr_stage_times(tr_handle *h, float *ms, int32_t count)
     int64_t calls = 0;
     for (int k = 0; k < TR_NUM_STAGES; ++k) calls += h->stage_calls[k];
     if (calls == 0) return TR_ERR_INVALID_ARG;
-    for (int k = 0; k < count; ++k)
-        ms[k] = h->stage_calls[k] ? (float)(h->stage_sum[k] / (double)h->stage_calls[k]) : 0.0f;
+    double avg[TR_NUM_STAGES];
+    for (int k = 0; k < TR_NUM_STAGES; ++k)
+        avg[k] = h->stage_calls[k] ? h->stage_sum[k] / (double)h->stage_calls[k] : 0.0;
+    // the hypothesis kernel's interval, split by the shares of its workgroups' time in each phase
+    // (in-kernel clock stamps summed over the profiled calls)
+    unsigned long long acc[kProfSlots];
+    if (hipMemcpy(acc, h->prof_acc, sizeof(acc), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemset(h->prof_acc, 0, sizeof(acc)) != hipSuccess)
+        return TR_ERR_HIP;
+    const double work = (double)acc[kProfSearch] + acc[kProfFit] + acc[kProfScore] + acc[kProfRecords] +
+                        acc[kProfSelect];
+    if (work > 0) {
+        const double hyp = avg[TR_STAGE_CLIQUES];
+        avg[TR_STAGE_CLIQUES] = hyp * acc[kProfSearch] / work;
+        avg[TR_STAGE_KABSCH] = hyp * acc[kProfFit] / work;
+        avg[TR_STAGE_SCORE] = hyp * (acc[kProfScore] + acc[kProfRecords]) / work;
+        avg[TR_STAGE_SELECT] = hyp * acc[kProfSelect] / work;
+    }
+    for (int k = 0; k < count; ++k) ms[k] = (float)avg[k];
     for (int k = 0; k < TR_NUM_STAGES; ++k) {
         h->stage_sum[k] = 0;
         h->stage_calls[k] = 0;

@@ -66,15 +66,20 @@ def correct_hypotheses(reg, torch, pairs, hs=(100, 200, 500, 1000, 2000), k2=2):
     return out
 
 
+def sweep_point(reg, torch, pairs, tau, k1, k2):
+    """Success rate and successful hypothesis poses per pair at one (tau, K1, K2)."""
+    ok = good = 0
+    for p in pairs:
+        r = _register(reg, torch, p, tau, p.cfg.theta, k1, k2)
+        ok += r.best_hyp >= 0 and synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
+        good += _counts(reg, p)[0]
+    return {"success_rate": ok / len(pairs), "successful_poses": good / len(pairs)}
+
+
 def sweep(reg, torch, pairs, taus=(0.025, 0.05, 0.1, 0.2, 0.4), k1s=(125, 250, 500, 1000),
           k2s=(1, 2, 3, 5, 8), tau0=0.1, k10=1000, k20=2):
     def run(tau, k1, k2):
-        ok = good = 0
-        for p in pairs:
-            r = _register(reg, torch, p, tau, p.cfg.theta, k1, k2)
-            ok += r.best_hyp >= 0 and synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
-            good += _counts(reg, p)[0]
-        return {"success_rate": ok / len(pairs), "successful_poses": good / len(pairs)}
+        return sweep_point(reg, torch, pairs, tau, k1, k2)
     return {"tau": {t: run(t, k10, k20) for t in taus}, "k1": {k: run(tau0, k, k20) for k in k1s},
             "k2": {k: run(tau0, k10, k) for k in k2s}}
 

@@ -63,3 +63,26 @@ def test_experiments_small(reg):
     cd = experiments.clique_discrepancy(reg, torch, taus=(0.02, 0.2), n=800, cliques=3)
     say(cd)
     assert cd[0.02]["cliques"] > 0 and cd[0.02]["fits"] > 0
+
+
+def oracle_sweep_point(pairs, tau, k1, k2):
+    """The same two numbers from the oracle's whole path and its own float64 fits."""
+    ok = good = 0
+    for p in pairs:
+        r, _, o = oracle.register_ex(p.src, p.dst, tau, p.cfg.theta, k1, k2)
+        ok += r.best_hyp >= 0 and synth.success(np.array(r.R).reshape(3, 3), np.array(r.t), p)
+        good += sum(synth.success(o["R"][h], o["t"][h], p) for h in np.nonzero(o["flags"] != 0)[0])
+    return {"success_rate": ok / len(pairs), "successful_poses": good / len(pairs)}
+
+
+@pytest.mark.parametrize("param,point", [("tau", (0.05, 150, 2)), ("k1", (0.1, 60, 2)), ("k2", (0.1, 150, 3))])
+def test_sweep_point_matches_oracle(reg, param, point):
+    # one point of each swept parameter: the success rate and the successful hypothesis poses per
+    # pair equal the oracle's (poses agree within 1e-4, far from the 15 deg / 30 cm thresholds)
+    from paper_2507_01439_amd import experiments
+    base = synth.CONFIGS["indoor_n1000"].replace(n=800, inlier_ratio=0.04)
+    pairs = [synth.make_pair(base, synth.pair_seed(11, 30 + b)) for b in range(3)]
+    got = experiments.sweep_point(reg, torch, pairs, *point)
+    want = oracle_sweep_point(pairs, *point)
+    say(param, point, got, want)
+    assert got == want

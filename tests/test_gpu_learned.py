@@ -126,6 +126,38 @@ def test_mlp_gradients_match_oracle(reg):
         assert rel_l2(a, b) < 2e-2, (k, rel_l2(a, b))
 
 
+def test_adam_steps_match_oracle(reg):
+    # four training steps (the first from zero moments, the others from the moments the GPU
+    # kept): each step's float32 weights against the oracle's float64 Adam on the same gradients
+    params = rand_params(21)
+    T.tr_scorer_set(reg.h, params)          # also resets the Adam state
+    rng = np.random.default_rng(22)
+    m = 1024
+    F = rng.random((m, 19)).astype(np.float32)
+    y = (rng.random(m) < 0.4).astype(np.uint8)
+    bits = (bf16(F).view(np.uint32) >> 16).astype(np.uint16)
+    d_feat = torch.from_numpy(bits.view(np.int16)).cuda()
+    d_lab = torch.from_numpy(y).cuda()
+    grads = torch.empty(T.TR_MLP_NPARAM, dtype=torch.float32, device="cuda")
+    w = params.astype(np.float64)
+    mo = np.zeros_like(w)
+    vo = np.zeros_like(w)
+    lr = 3e-3
+    for t in range(1, 5):
+        T.tr_mlp_grads(reg.h, d_feat, d_lab, m, grads)          # the gradients the step will use
+        T.tr_train_step(reg.h, d_feat, d_lab, m, lr)
+        torch.cuda.synchronize()
+        g = grads.cpu().numpy().astype(np.float64)
+        w_gpu = T.tr_scorer_get(reg.h).astype(np.float64)
+        oracle.adam(w, g, mo, vo, t, lr)
+        tol = 4 * np.spacing(np.abs(w).astype(np.float32)).astype(np.float64) + 1e-5 * lr
+        err = np.abs(w_gpu - w)
+        say(f"adam step {t}: max |dw| {np.abs(w_gpu - params).max():.3e}, max err {err.max():.3e}")
+        assert (err <= tol).all(), (t, int(np.argmax(err - tol)), float(err.max()))
+        assert np.abs(w_gpu - params).max() > 0
+        w = w_gpu.copy()                      # the next step starts from the GPU's float32 weights
+
+
 def test_training_lowers_loss_and_blob_roundtrip(reg):
     T.tr_scorer_set(reg.h, rand_params(5, scale=0.1))
     # features and labels of generated pairs
@@ -196,3 +228,27 @@ def test_learned_fallback_on_nonfinite_scores(reg):
     assert r.status == T.TR_WARN_SCORER_FALLBACK
     plain = reg.debug(T.TR_TAP_PLAIN_PIVOTS)
     assert np.array_equal(reg.debug(T.TR_TAP_PIVOTS), plain[:cfg.k1])
+
+
+def test_trained_scorer_gain_on_held_out_hard_pairs():
+    # What the committed network gains: on 64 held-out pairs of the hard slice (N = 5000,
+    # 0.5-1 % inliers, seeds disjoint from training), learned pivots reach the success rate of
+    # plain pivots at K1 = 1000 with fewer pivots than plain pivots need.
+    import os
+    from paper_2507_01439_amd import eval_learned
+    weights = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2507_01439_amd",
+                           "weights", "scorer_indoor.bin")
+    r = T.Registrar(max_n=5000, max_batch=1, max_k1=1000, max_k2=2)
+    try:
+        with open(weights, "rb") as f:
+            T.tr_scorer_load(r.h, f.read())
+        _, hard = eval_learned.held_out(0, 64)
+        res = eval_learned.compare(r, torch, hard, k1_sweep=(8, 16, 32, 64, 125, 250, 1000), ref_k1=1000)
+    finally:
+        r.close()
+    tab = {m: {k: round(v["success_rate"], 3) for k, v in res["table"][m].items()} for m in res["table"]}
+    say(tab, res["operating_k1"])
+    op = res["operating_k1"]
+    assert op["learned"] is not None and op["plain"] is not None
+    assert op["learned"] < op["plain"]
+    assert all(tab["learned"][k] >= tab["plain"][k] for k in (8, 16, 32, 64))

@@ -249,3 +249,20 @@ def test_compat_guard_band_stress():
         say(f"edges {r.n_edges} boundary {b32}")
     finally:
         big.close()
+
+
+@pytest.mark.parametrize("block", [300, 600])
+def test_dense_and_sparse_tiles_in_one_pair(reg, block):
+    # the first `block` matches are one rigid copy (all mutually compatible), the rest uniform
+    # outliers: the SC2 tiles over that block hold more edges than the bit-count path takes and
+    # run on MFMA, the other tiles take the bit-count path; every weight against the oracle
+    rng = np.random.default_rng(block)
+    n = 1400
+    X = ((rng.random((n, 3)) - 0.5) * 3.0).astype(np.float32)
+    Y = ((rng.random((n, 3)) - 0.5) * 3.0).astype(np.float32)
+    Y[:block] = X[:block] + np.float32(0.5)
+    prm = T.make_params(0.1, 0.1, k1=400, k2=2)
+    say(f"dense block {block} in n={n}")
+    r, mask = run_single(reg, torch, X, Y, prm)
+    check_taps(reg, X, Y, prm, r, mask, label=f"dense block {block}")
+    assert r.best_inliers >= block

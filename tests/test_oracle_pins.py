@@ -633,3 +633,30 @@ def test_openmp_build_computes_the_same_bits():
     assert np.array_equal(C1, C2) and (b1, b64, f1) == (b2, b642, f2)
     assert np.array_equal(G1, G2) and np.array_equal(P1, P2) and n1 == n2 and np.array_equal(cl1, cl2)
     assert bytes(r1) == bytes(r2) and np.array_equal(m1, m2)
+
+
+def test_register_ex_options():
+    # the generalised whole path: without options it is tro_register; constant scores keep the
+    # plain order (ties by plain rank), so the learned path equals the plain one; scores from the
+    # generator's labels put every pool pivot joining two inliers first, in plain order within
+    # each key; scoring the path's own float32 poses changes nothing; the per-hypothesis
+    # outputs satisfy the closed forms they follow (IN counts the mask of each pose)
+    cfg = synth.CONFIGS["indoor_n1000"].replace(n=300, k1=40, inlier_ratio=0.1)
+    p = synth.make_pair(cfg, synth.pair_seed(0, 41))
+    args = (p.src, p.dst, cfg.tau, cfg.theta, cfg.k1, cfg.k2)
+    r0, m0 = oracle.register(*args)
+    r1, m1, o1 = oracle.register_ex(*args)
+    assert bytes(r0) == bytes(r1) and np.array_equal(m0, m1)
+    r2, m2, o2 = oracle.register_ex(*args, pool_factor=4, scores=np.full(300, 0.25, np.float32))
+    assert bytes(r0) == bytes(r2) and np.array_equal(m0, m2) and np.array_equal(o1["cliques"], o2["cliques"])
+    poses = np.concatenate([o1["R"].reshape(-1, 9), o1["t"]], axis=1).astype(np.float32)
+    r3, m3, o3 = oracle.register_ex(*args, poses=poses)
+    assert bytes(r0) == bytes(r3) and np.array_equal(o1["IN"], o3["IN"])
+    for h in np.nonzero(o1["flags"] != 0)[0][:20]:
+        assert o1["IN"][h] == oracle.mask(p.src, p.dst, poses[h], cfg.theta).sum()
+    lab = p.labels.astype(np.float32)
+    r4, m4, o4 = oracle.register_ex(*args, pool_factor=4, scores=lab)
+    pool, npool = oracle.pivots(oracle.o2graph(oracle.sc2(oracle.compat(p.src, p.dst, cfg.tau)[0])), 4 * cfg.k1)
+    key = [-(lab[i] + lab[j]) for i, j, _ in pool[:npool]]
+    order = sorted(range(npool), key=lambda r: (key[r], r))
+    assert o4["pivots"].tolist() == pool[order[:cfg.k1]].tolist()
