@@ -70,9 +70,10 @@ __device__ __forceinline__ void adj_col(const double (&A)[4][4], double (&v)[4])
 //   det(lambda I - K) = lambda^4 - tr(K^2)/2 lambda^2 - tr(K^3)/3 lambda + det K
 // from E0 = (sum |p_a|^2 + sum |q_a|^2)/2, an upper bound of the root, until
 // the step falls below 1e-15 relative or stops being positive. The
-// eigenvector is the largest column of adj(K - lambda I). When that column
-// vanishes (a repeated top eigenvalue: collinear or coincident points) the
-// cyclic Jacobi method on K decides instead. float64 throughout, then R and t
+// eigenvector is the largest column of adj(K - lambda I). When the top
+// eigenvalue is repeated or nearly so (collinear, nearly collinear or
+// coincident points), where that column loses its accuracy, the cyclic Jacobi
+// method on K decides instead. float64 throughout, then R and t
 // are rounded to float32. An empty clique (z < 0) gives the identity and false.
 __device__ bool fit_pose(const Work &w, const PairDesc &d, int ia, int ib, int ic, float (&pose)[12])
 {
@@ -164,9 +165,16 @@ __device__ bool fit_pose(const Work &w, const PairDesc &d, int ia, int ib, int i
         take();
         adj_col<3>(A, cand);
         take();
-        const double scale3 = E0 * E0 * E0;
-        if (!(best > 1e-24 * scale3 * scale3) || !(best < 1e300)) {
-            // repeated top eigenvalue (or no spread at all): cyclic Jacobi on K
+        // The adjugate column has norm between P/2 and P, P = prod_{k>1} (lambda_1 - lambda_k). K's
+        // spectrum for three matches is +-(s1 + s2), +-(s1 - s2) (s1 >= s2 the singular values of
+        // M), so P ~ 4 lambda^3 g with g the relative gap to the second eigenvalue. Near a double
+        // root the Newton root carries an error ~ eps lambda / g and the adjugate vector one of
+        // ~ eps / g^2 (3.6e-4 rad at g = 6e-7 on nearly collinear outdoor cliques); below
+        // g ~ 1e-4 the Jacobi method decides, whose error is ~ eps / g.
+        const double scale3 = E0 * E0 * E0, lam3 = lam * lam * lam;
+        if (!(best > 1e-24 * scale3 * scale3) || !(best < 1e300) || !(best > 1.6e-7 * lam3 * lam3)) {
+            // repeated or nearly repeated top eigenvalue (nearly collinear or coincident points,
+            // or no spread at all): cyclic Jacobi on K
             double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
             double fro = 0;
 #pragma unroll

@@ -143,3 +143,27 @@ def success(R_est, t_est, pair: Pair) -> bool:
     if pair.cfg.outdoor:
         return re <= 5.0 and te <= 0.6
     return re < 15.0 and te < 0.30
+
+
+def near_collinear_triplets(seed: int, count: int, box=(100.0, 100.0, 10.0), sigma: float = 0.05,
+                            log10_off=(-6.0, -1.0)):
+    """`count` match triplets whose source points lie nearly on a line, for the conditioning of
+    three-point fits: a and b uniform in the box, c = a + u (b - a) + e n with u ~ U[-0.5, 1.5],
+    n a unit vector orthogonal to b - a and e = 10^U(log10_off) metres; targets are a rigid
+    motion of the sources plus N(0, sigma^2 I) noise. Returns (X, Y) float32 (3 count x 3) and
+    the cliques int32 (count x 3) = (3k, 3k+1, 3k+2)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    box = np.asarray(box, dtype=np.float64)
+    R = random_rotation(rng)
+    t = _ball(rng, 1.0)
+    X = np.empty((3 * count, 3))
+    for k in range(count):
+        a, b = (rng.random((2, 3)) - 0.5) * box
+        d = b - a
+        n = np.cross(d, rng.standard_normal(3))
+        n /= np.linalg.norm(n)
+        c = a + rng.uniform(-0.5, 1.5) * d + 10.0 ** rng.uniform(*log10_off) * n
+        X[3 * k:3 * k + 3] = (a, b, c)
+    Y = X @ R.T + t + rng.standard_normal(X.shape) * sigma
+    cl = np.arange(3 * count, dtype=np.int32).reshape(count, 3)
+    return (np.ascontiguousarray(X, dtype=np.float32), np.ascontiguousarray(Y, dtype=np.float32), cl)

@@ -332,6 +332,54 @@ def test_kabsch_reflection_and_degenerate():
     assert fl[0] == 0 and np.array_equal(R[0], np.eye(3)) and not t.any()
 
 
+def _fit_mp(p, q, digits=40):
+    """Least-squares rotation and translation of three matches in `digits`-digit arithmetic
+    (mpmath): Horn's quaternion eigenproblem on the exact inputs, an independent method at
+    a precision where rounding plays no part at the tested conditioning."""
+    import mpmath as mp
+    with mp.workdps(digits):
+        P = [[mp.mpf(float(v)) for v in r] for r in p]
+        Q = [[mp.mpf(float(v)) for v in r] for r in q]
+        pb = [sum(P[a][k] for a in range(3)) / 3 for k in range(3)]
+        qb = [sum(Q[a][k] for a in range(3)) / 3 for k in range(3)]
+        M = [[sum((P[a][r] - pb[r]) * (Q[a][s] - qb[s]) for a in range(3)) for s in range(3)] for r in range(3)]
+        (xx, xy, xz), (yx, yy, yz), (zx, zy, zz) = M
+        K = mp.matrix([[xx + yy + zz, yz - zy, zx - xz, xy - yx],
+                       [yz - zy, xx - yy - zz, xy + yx, zx + xz],
+                       [zx - xz, xy + yx, yy - xx - zz, yz + zy],
+                       [xy - yx, zx + xz, yz + zy, zz - xx - yy]])
+        E, V = mp.eigsy(K)
+        k = max(range(4), key=lambda i: E[i])
+        w, x, y, z = (V[r, k] for r in range(4))
+        R = mp.matrix([[w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                       [2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)],
+                       [2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z]])
+        t = [qb[r] - sum(R[r, c] * pb[c] for c in range(3)) for r in range(3)]
+        return (np.array([[float(R[r, c]) for c in range(3)] for r in range(3)]),
+                np.array([float(v) for v in t]))
+
+
+def test_kabsch_nearly_collinear_matches_extended_precision():
+    """Nearly collinear triplets at outdoor scale (sources within 1e-6..1e-1 m of a line through
+    points up to 100 m from the origin): the rotation about the line is decided by a singular
+    value down to ~1e-8 of the largest, the regime where eigenvalue-based fits lose accuracy.
+    The oracle's fit equals the 40-digit solution within 1e-7 rad and 1e-5 m (Section 3.5)."""
+    X, Y, cl = synth.near_collinear_triplets(31, 60)
+    R, t, fl = oracle.kabsch(X, Y, cl)
+    checked, ratios = 0, []
+    for h in range(len(cl)):
+        if fl[h] != 1:   # sigma_2 <= 1e-9 sigma_1: reported as degenerate, no unique rotation
+            continue
+        p, q = X[cl[h]].astype(np.float64), Y[cl[h]].astype(np.float64)
+        s = np.linalg.svd((p - p.mean(0)).T @ (q - q.mean(0)), compute_uv=False)
+        ratios.append(s[1] / s[0])
+        Re, te = _fit_mp(p, q)
+        d = np.linalg.norm(R[h] - Re)
+        assert 2 * math.asin(min(1.0, d / (2 * math.sqrt(2)))) <= 1e-7, h
+        assert np.abs(t[h] - te).max() <= 1e-5, h
+        checked += 1
+    assert checked >= 40 and min(ratios) < 1e-7 and sum(r < 1e-5 for r in ratios) >= 10
+
 # ---------------------------------------------------------------- Eq. 9
 
 def test_score_matches_float64_count_off_boundary():
