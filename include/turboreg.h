@@ -30,6 +30,7 @@ extern "C" {
 #endif
 
 #define TR_MAX_K2 8          /* largest supported K2 (cliques per pivot)              */
+#define TR_SC2_SPARSE_CAP_MAX 8192   /* largest tr_tuning.sc2_sparse_cap               */
 #define TR_MAX_POOL 16384    /* largest pivot list one workgroup sorts (K1 or pool)  */
 #define TR_MLP_IN 19         /* learned scorer: features per correspondence           */
 #define TR_MLP_HID 64        /* learned scorer: hidden width                          */
@@ -142,7 +143,7 @@ tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32
  * Calls are grouped by shape: the number of 256-row tiles of their largest
  * pair, round_up(max_n, 256) / 256, and the batch size B (1 for tr_register).
  * Each group has a launch configuration; a group never tuned or set uses the
- * defaults (5, 4, 4 for one pair or 16 for a batch, 4). No configuration
+ * defaults (5, 4, 4 for one pair or 16 for a batch, 4, 0). No configuration
  * changes any result: C, weights, pivots, cliques, poses, inlier numbers and
  * the selection are the same under every valid configuration. */
 typedef struct {
@@ -151,6 +152,10 @@ typedef struct {
     int32_t compat_per_cu;  /* compatibility work items launched per CU, 1..16     */
     int32_t hyp_ppw;        /* pivots per hypothesis work item: 4, 8, 12 or 16     */
     int32_t hyp_per_cu;     /* hypothesis workgroups launched per CU, 1..16        */
+    int32_t sc2_sparse_cap; /* SC2 output tiles (256 x 256) with at most this many
+                               edges count common neighbours per edge from bit rows
+                               instead of the dense product; 0 = every tile takes
+                               the product. 0..TR_SC2_SPARSE_CAP_MAX             */
 } tr_tuning;
 
 /* Configuration of the group of (max_n, B). TR_ERR_INVALID_ARG for max_n < 3, B < 1. */
@@ -162,7 +167,7 @@ tr_status tr_tuning_set(tr_handle *h, int32_t max_n, int32_t B, const tr_tuning 
 /* Autotuner: runs the registration of the given inputs (one pair of N = max_n
  * if offsets_dev is NULL and B == 1, else the batch as tr_register_batch) under
  * candidate configurations, one field at a time starting from the group's
- * current one (hyp_ppw, hyp_per_cu, sc2_super, compat_per_cu), each candidate
+ * current one (hyp_ppw, hyp_per_cu, sc2_super, compat_per_cu, sc2_sparse_cap), each candidate
  * timed by HIP events on `stream` over five runs after one warm-up, keeps a
  * candidate only if it is at least 1% faster, stores the result for the group
  * and writes it to *best (nullable) with its time per registration call in

@@ -68,6 +68,8 @@ struct Work {
     int32_t H;                // k1 * k2 hypotheses per pair
     int32_t graph;
     int32_t sc2_super;        // SC2 tile walk: super-tile side in output tiles (launch configuration)
+    int32_t sc2_sparse_cap;   // SC2 tiles with at most this many edges take the bit-count path; 0: none
+                              // does, and Cbits is not written (launch configuration)
     float tau, theta;
     uint8_t *C;               // C arena (E2M1 nibbles, the MFMA operands)
     uint8_t *Cbits;           // C arena as bits: per pair npad x npad bits in blocks of 128 columns,

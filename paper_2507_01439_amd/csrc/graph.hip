@@ -195,7 +195,7 @@ __device__ __forceinline__ bool near_tau(float la, float lb, float dl, float tau
 // (boundary pairs, edges) go to a per-item slot, so no atomics are needed;
 // non-finite inputs are counted by the diagonal tiles (third slot), which also clear the
 // pair's weight histograms and row maxima for their rows.
-template <bool LEARNED>
+template <bool LEARNED, bool BITS>
 __global__ void __launch_bounds__(256, 2) k_compat(Work w)
 {
     __shared__ float px[2][64][3], py[2][64][3];
@@ -372,8 +372,8 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         if (!diag)
             *reinterpret_cast<uint2 *>(Cb + ((int64_t)bj * kCompatTile + r) * rs + bi * (kCompatTile / 2) + c8) =
                 *reinterpret_cast<const uint2 *>(&tile[1][r * kNibStride + c8]);
-        if (tid < (diag ? 64 : 128)) {
-            // the same rows as bits (threads 0-63: the tile's rows, 64-127: its transpose), 8 bytes per
+        if (BITS && tid < (diag ? 64 : 128)) {
+            // the same rows as bits (read only by the SC2 bit-count path) (threads 0-63: the tile's rows, 64-127: its transpose), 8 bytes per
             // row into the 16-byte piece of the row's 128-column block
             const int side = tid >> 6, rr = tid & 63;
             const uint4 *src = reinterpret_cast<const uint4 *>(&tile[side][rr * kNibStride]);
@@ -423,9 +423,11 @@ static_assert(kTileBytes <= kRingBytes, "the finished tile must fit the ring");
 constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then the low 16 bits of 2^23 + v
 // Bit-count path (tiles with few edges): Eq. 2 is needed only where C_ij = 1, so a tile holding at
 // most kSddmmCap edges counts popcount(row_i AND row_j) for each of its edges instead of forming
-// the dense product. Rows arrive in chunks of kChunkKb 128-column blocks (bits); LDS layout:
+// the dense product (the threshold is a launch parameter up to kSddmmCap; 0 turns the path and the
+// compatibility kernel's bit rows off). Rows arrive in chunks of kChunkKb 128-column blocks (bits); LDS layout:
 // two chunk buffers (I rows then J rows, [block][row][16 bytes] each), the edge list, the counts.
 constexpr int kSddmmCap = 8192;                       // 32 edges per thread
+static_assert(kSddmmCap == TR_SC2_SPARSE_CAP_MAX, "the launch parameter's range is the path's capacity");
 constexpr int kChunkKb = 4;                           // 512 columns of C per chunk
 constexpr int kChunkSide = kChunkKb * kSc2Tile * 16;  // 16 KiB: one side's 256 rows of a chunk
 constexpr int kChunkBytes = 2 * kChunkSide;
@@ -485,7 +487,7 @@ __device__ __forceinline__ int half_sum(int v)
 // kHistGroups copies per pair) and reduced into the per-row maximum of the
 // upper triangle. In learned mode it also adds row and column sums / maxima
 // of the symmetric SC2 matrix for the per-match features.
-template <bool LEARNED>
+template <bool LEARNED, bool SPARSE>
 __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
 {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
@@ -514,36 +516,39 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         const uint8_t *Cbit = w.Cbits + d.c_off / 8;
         const int64_t kbs = (int64_t)d.npad * 16;   // bytes of one 128-column block over all rows
         const bool diag = bi == bj;
-        uint32_t mw[8];
-        {
+        uint32_t mw[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (SPARSE) {
             const int64_t ro = ((int64_t)bi * kSc2Tile + tid) * 16;
             const uint4 m0 = *reinterpret_cast<const uint4 *>(Cbit + (2 * bj) * kbs + ro);
             const uint4 m1 = *reinterpret_cast<const uint4 *>(Cbit + (2 * bj + 1) * kbs + ro);
             mw[0] = m0.x; mw[1] = m0.y; mw[2] = m0.z; mw[3] = m0.w;
             mw[4] = m1.x; mw[5] = m1.y; mw[6] = m1.z; mw[7] = m1.w;
         }
-        int ecount = 0;
+        int ecount = 0, eprefix = 0, etotal = 0;
+        bool sparse = false;
+        if (SPARSE) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (diag) {   // i < j only: columns above the thread's row
-                const int lo = tid + 1 - 32 * k;
-                mw[k] &= lo <= 0 ? 0xFFFFFFFFu : (lo >= 32 ? 0u : (0xFFFFFFFFu << lo));
+            for (int k = 0; k < 8; ++k) {
+                if (diag) {   // i < j only: columns above the thread's row
+                    const int lo = tid + 1 - 32 * k;
+                    mw[k] &= lo <= 0 ? 0xFFFFFFFFu : (lo >= 32 ? 0u : (0xFFFFFFFFu << lo));
+                }
+                ecount += __builtin_popcount(mw[k]);
             }
-            ecount += __builtin_popcount(mw[k]);
-        }
-        int32_t *scanL = reinterpret_cast<int32_t *>(smem + kScanOff);
-        int eprefix = ecount;   // inclusive scan inside the wave, then the waves before
+            int32_t *scanL = reinterpret_cast<int32_t *>(smem + kScanOff);
+            eprefix = ecount;   // inclusive scan inside the wave, then the waves before
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(eprefix, o, 64);
-            if (lane >= o) eprefix += y;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(eprefix, o, 64);
+                if (lane >= o) eprefix += y;
+            }
+            if (lane == 63) scanL[wv] = eprefix;
+            __syncthreads();
+            etotal = scanL[0] + scanL[1] + scanL[2] + scanL[3];
+            for (int v = 0; v < wv; ++v) eprefix += scanL[v];
+            eprefix -= ecount;   // exclusive
+            sparse = etotal <= w.sc2_sparse_cap;
         }
-        if (lane == 63) scanL[wv] = eprefix;
-        __syncthreads();
-        const int etotal = scanL[0] + scanL[1] + scanL[2] + scanL[3];
-        for (int v = 0; v < wv; ++v) eprefix += scanL[v];
-        eprefix -= ecount;   // exclusive
-        const bool sparse = etotal <= kSddmmCap;
         if (sparse) {
             uint16_t *edgeL = reinterpret_cast<uint16_t *>(smem + kEdgeOff);
             int32_t *cntL = reinterpret_cast<int32_t *>(smem + kCntOff);
@@ -901,25 +906,35 @@ hipError_t launch_prep_learned(const Work &w, int grid, hipStream_t s)
 
 hipError_t launch_compat(const Work &w, int grid, hipStream_t s)
 {
-    if (w.learned && w.feat_all) hipLaunchKernelGGL(k_compat<true>, dim3(grid), dim3(256), 0, s, w);
-    else hipLaunchKernelGGL(k_compat<false>, dim3(grid), dim3(256), 0, s, w);
+    // the bit rows are written only for an SC2 launch that may take the bit-count path
+    const bool learned = w.learned && w.feat_all, bits = w.sc2_sparse_cap > 0;
+    if (learned && bits) hipLaunchKernelGGL((k_compat<true, true>), dim3(grid), dim3(256), 0, s, w);
+    else if (learned) hipLaunchKernelGGL((k_compat<true, false>), dim3(grid), dim3(256), 0, s, w);
+    else if (bits) hipLaunchKernelGGL((k_compat<false, true>), dim3(grid), dim3(256), 0, s, w);
+    else hipLaunchKernelGGL((k_compat<false, false>), dim3(grid), dim3(256), 0, s, w);
     return hipGetLastError();
 }
 
 hipError_t launch_sc2(const Work &w, int grid, hipStream_t s)
 {
-    if (w.learned) hipLaunchKernelGGL(k_sc2<true>, dim3(grid), dim3(256), kSc2Lds, s, w);
-    else hipLaunchKernelGGL(k_sc2<false>, dim3(grid), dim3(256), kSc2Lds, s, w);
+    // separate instances: the dense-only kernel carries none of the bit-count path's registers
+    const bool sparse = w.sc2_sparse_cap > 0;
+    if (w.learned && sparse) hipLaunchKernelGGL((k_sc2<true, true>), dim3(grid), dim3(256), kSc2Lds, s, w);
+    else if (w.learned) hipLaunchKernelGGL((k_sc2<true, false>), dim3(grid), dim3(256), kSc2Lds, s, w);
+    else if (sparse) hipLaunchKernelGGL((k_sc2<false, true>), dim3(grid), dim3(256), kSc2Lds, s, w);
+    else hipLaunchKernelGGL((k_sc2<false, false>), dim3(grid), dim3(256), kSc2Lds, s, w);
     return hipGetLastError();
 }
 
 hipError_t setup_graph_kernels()
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kSc2Lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sc2<true>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                kSc2Lds);
+    const void *fns[4] = {reinterpret_cast<const void *>(k_sc2<false, false>),
+                          reinterpret_cast<const void *>(k_sc2<false, true>),
+                          reinterpret_cast<const void *>(k_sc2<true, false>),
+                          reinterpret_cast<const void *>(k_sc2<true, true>)};
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 4 && e == hipSuccess; ++k)
+        e = hipFuncSetAttribute(fns[k], hipFuncAttributeMaxDynamicSharedMemorySize, kSc2Lds);
     return e;
 }
 

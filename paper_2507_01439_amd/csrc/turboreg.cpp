@@ -181,13 +181,15 @@ tr_tuning tuning_for(const tr_handle *h, int32_t max_n, int32_t B)
     t.compat_per_cu = 4;
     t.hyp_ppw = B == 1 ? 4 : 16;   // batches: more pivots per workgroup, fewer passes over each pair's matches
     t.hyp_per_cu = 4;
+    t.sc2_sparse_cap = 0;
     return t;
 }
 
 bool tuning_valid(const tr_tuning &t)
 {
     return t.sc2_super >= 1 && t.sc2_super <= 16 && t.compat_per_cu >= 1 && t.compat_per_cu <= 16 &&
-           t.hyp_ppw >= 4 && t.hyp_ppw <= 16 && t.hyp_ppw % 4 == 0 && t.hyp_per_cu >= 1 && t.hyp_per_cu <= 16;
+           t.hyp_ppw >= 4 && t.hyp_ppw <= 16 && t.hyp_ppw % 4 == 0 && t.hyp_per_cu >= 1 && t.hyp_per_cu <= 16 &&
+           t.sc2_sparse_cap >= 0 && t.sc2_sparse_cap <= TR_SC2_SPARSE_CAP_MAX;
 }
 
 int grid_cap(tr_handle *h, int64_t items, int per_cu)
@@ -215,6 +217,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.H = p.k1 * p.k2;
     w.graph = p.graph;
     w.sc2_super = 5;
+    w.sc2_sparse_cap = 0;
     w.tau = p.tau;
     w.theta = p.inlier_thresh;
     w.C = h->C;
@@ -284,6 +287,7 @@ tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_
     if (!ev_mask) ev_mask = &ev_mask_unused;
     Work w = w_in;
     w.sc2_super = cfg.sc2_super;
+    w.sc2_sparse_cap = cfg.sc2_sparse_cap;
     const bool profile = ev != nullptr;
     const int64_t npad = (max_n + kSc2Tile - 1) / kSc2Tile * kSc2Tile;
     const int64_t nb64 = npad / kCompatTile, nbs = npad / kSc2Tile;
@@ -615,7 +619,8 @@ tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const in
     tr_tuning cur = tuning_for(h, max_n, B);
     float cur_ms = 0.0f;
     st = time_cfg(cur, cur_ms);
-    static const int kPpw[] = {4, 8, 16}, kPerCu[] = {2, 4, 8}, kSuper[] = {3, 4, 5, 6, 8}, kCompat[] = {2, 4, 8};
+    static const int kPpw[] = {4, 8, 16}, kPerCu[] = {2, 4, 8}, kSuper[] = {3, 4, 5, 6, 8}, kCompat[] = {2, 4, 8},
+                     kSparse[] = {0, 1024, 2048, 4096, TR_SC2_SPARSE_CAP_MAX};
     struct Field {
         int32_t tr_tuning::*f;
         const int *v;
@@ -624,7 +629,8 @@ tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const in
     const Field fields[] = {{&tr_tuning::hyp_ppw, kPpw, 3},
                             {&tr_tuning::hyp_per_cu, kPerCu, 3},
                             {&tr_tuning::sc2_super, kSuper, 5},
-                            {&tr_tuning::compat_per_cu, kCompat, 3}};
+                            {&tr_tuning::compat_per_cu, kCompat, 3},
+                            {&tr_tuning::sc2_sparse_cap, kSparse, 5}};
     for (const Field &fd : fields) {
         const int32_t start = cur.*fd.f;
         for (int k = 0; k < fd.n && st == TR_OK; ++k) {

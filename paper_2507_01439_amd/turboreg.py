@@ -21,6 +21,7 @@ TR_GRAPH_O2, TR_GRAPH_SC2 = 0, 1
 TR_PIVOTS_PLAIN, TR_PIVOTS_LEARNED = 0, 1
 TR_FLAG_PROFILE, TR_FLAG_PROFILE_SC2, TR_FLAG_RANK_MAE, TR_FLAG_RANK_MSE = 1, 2, 4, 8
 TR_MAX_K2 = 8
+TR_SC2_SPARSE_CAP_MAX = 8192
 TR_MLP_NPARAM = 5505
 (TR_TAP_C, TR_TAP_G, TR_TAP_PIVOTS, TR_TAP_CLIQUES, TR_TAP_POSES, TR_TAP_IN, TR_TAP_FEATURES,
  TR_TAP_SCORES, TR_TAP_PLAIN_PIVOTS, TR_TAP_RANK_SCORES) = range(10)
@@ -48,10 +49,10 @@ class tr_result(ct.Structure):
 
 class tr_tuning(ct.Structure):
     _fields_ = [("sc2_super", ct.c_int32), ("compat_per_cu", ct.c_int32), ("hyp_ppw", ct.c_int32),
-                ("hyp_per_cu", ct.c_int32)]
+                ("hyp_per_cu", ct.c_int32), ("sc2_sparse_cap", ct.c_int32)]
 
 
-assert ct.sizeof(tr_result) == 80 and ct.sizeof(tr_params) == 32 and ct.sizeof(tr_tuning) == 16
+assert ct.sizeof(tr_result) == 80 and ct.sizeof(tr_params) == 32 and ct.sizeof(tr_tuning) == 20
 
 _lib = None
 

@@ -262,7 +262,13 @@ def test_dense_and_sparse_tiles_in_one_pair(reg, block):
     Y = ((rng.random((n, 3)) - 0.5) * 3.0).astype(np.float32)
     Y[:block] = X[:block] + np.float32(0.5)
     prm = T.make_params(0.1, 0.1, k1=400, k2=2)
-    say(f"dense block {block} in n={n}")
-    r, mask = run_single(reg, torch, X, Y, prm)
-    check_taps(reg, X, Y, prm, r, mask, label=f"dense block {block}")
-    assert r.best_inliers >= block
+    default = T.tr_tuning_get(reg.h, n, 1)
+    T.tr_tuning_set(reg.h, n, 1, T.tr_tuning(default.sc2_super, default.compat_per_cu, default.hyp_ppw,
+                                             default.hyp_per_cu, T.TR_SC2_SPARSE_CAP_MAX))
+    try:
+        say(f"dense block {block} in n={n}")
+        r, mask = run_single(reg, torch, X, Y, prm)
+        check_taps(reg, X, Y, prm, r, mask, label=f"dense block {block}")
+        assert r.best_inliers >= block
+    finally:
+        T.tr_tuning_set(reg.h, n, 1, default)

@@ -35,17 +35,17 @@ def same(a, b):
     return all(np.array_equal(x.view(np.uint8), y.view(np.uint8)) for x, y in zip(a, b))
 
 
-def cfg(sup, compat, ppw, per_cu):
-    return T.tr_tuning(sup, compat, ppw, per_cu)
+def cfg(sup, compat, ppw, per_cu, sparse=0):
+    return T.tr_tuning(sup, compat, ppw, per_cu, sparse)
 
 
 def test_defaults_and_argument_errors(reg):
     d1 = T.tr_tuning_get(reg.h, 5000, 1)
-    assert (d1.sc2_super, d1.compat_per_cu, d1.hyp_ppw, d1.hyp_per_cu) == (5, 4, 4, 4)
+    assert (d1.sc2_super, d1.compat_per_cu, d1.hyp_ppw, d1.hyp_per_cu, d1.sc2_sparse_cap) == (5, 4, 4, 4, 0)
     d8 = T.tr_tuning_get(reg.h, 1500, 8)
     assert d8.hyp_ppw == 16
     for bad in (cfg(0, 4, 4, 4), cfg(17, 4, 4, 4), cfg(5, 0, 4, 4), cfg(5, 4, 6, 4), cfg(5, 4, 20, 4),
-                cfg(5, 4, 4, 0), cfg(5, 4, 4, 17)):
+                cfg(5, 4, 4, 0), cfg(5, 4, 4, 17), cfg(5, 4, 4, 4, -1), cfg(5, 4, 4, 4, T.TR_SC2_SPARSE_CAP_MAX + 1)):
         with pytest.raises(T.TurboRegError) as e:
             T.tr_tuning_set(reg.h, 1000, 1, bad)
         assert e.value.status == T.TR_ERR_INVALID_ARG
@@ -61,8 +61,10 @@ def test_single_pair_results_do_not_depend_on_configuration(reg):
     try:
         r0, m0 = run_single(reg, torch, p.src, p.dst, prm)
         ref = snapshot(reg, r0, m0)
-        for k, t in enumerate([cfg(1, 1, 8, 1), cfg(16, 16, 16, 16), cfg(3, 2, 12, 2), cfg(8, 8, 4, 8)]):
-            say(f"configuration {k}: super {t.sc2_super} compat {t.compat_per_cu} ppw {t.hyp_ppw} per_cu {t.hyp_per_cu}")
+        for k, t in enumerate([cfg(1, 1, 8, 1), cfg(16, 16, 16, 16, 8192), cfg(3, 2, 12, 2, 1024),
+                               cfg(8, 8, 4, 8, 3000)]):
+            say(f"configuration {k}: super {t.sc2_super} compat {t.compat_per_cu} ppw {t.hyp_ppw} per_cu {t.hyp_per_cu} "
+                f"sparse {t.sc2_sparse_cap}")
             T.tr_tuning_set(reg.h, c.n, 1, t)
             assert T.tr_tuning_get(reg.h, c.n, 1).hyp_ppw == t.hyp_ppw
             r, m = run_single(reg, torch, p.src, p.dst, prm)
