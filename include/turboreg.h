@@ -31,6 +31,9 @@ extern "C" {
 
 #define TR_MAX_K2 8          /* largest supported K2 (cliques per pivot)              */
 #define TR_SC2_SPARSE_CAP_MAX 8192   /* largest tr_tuning.sc2_sparse_cap               */
+#define TR_NOALLOC_MAX_N 2048        /* largest n of tr_register_noalloc                */
+#define TR_NOALLOC_MAX_K1 1024       /* largest k1 of tr_register_noalloc               */
+#define TR_NOALLOC_SCRATCH_BYTES (13u << 20)   /* its static workspace per device       */
 #define TR_MAX_POOL 16384    /* largest pivot list one workgroup sorts (K1 or pool)  */
 #define TR_MLP_IN 19         /* learned scorer: features per correspondence           */
 #define TR_MLP_HID 64        /* learned scorer: hidden width                          */
@@ -106,6 +109,21 @@ tr_status tr_destroy(tr_handle *h);
  * under the selected pose. `stream` is a hipStream_t (NULL = default stream). */
 tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t n,
                       const tr_params *p, tr_result *out_dev, uint8_t *mask_dev, void *stream);
+
+/* Register one pair with no allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid it): the same
+ * launch sequence as tr_register with its default launch configuration, on the calling
+ * thread's current device, but its workspace is a fixed static device array of
+ * TR_NOALLOC_SCRATCH_BYTES per device (held until the process ends), so no handle is needed.
+ * Limits: 3 <= n <= TR_NOALLOC_MAX_N, k1 <= TR_NOALLOC_MAX_K1, k2 <= TR_MAX_K2 (larger ->
+ * TR_ERR_WORKSPACE); plain pivots only and no TR_FLAG_PROFILE* flags (TR_ERR_INVALID_ARG).
+ * The first call on a device resolves the array's address there and may return TR_ERR_HIP.
+ * Every call on one device shares that device's array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller. The kernels clear every
+ * counter they use at the start of each call, so no state carries over between calls.
+ * Arguments as tr_register; outputs are bit-identical to tr_register's on the same inputs. */
+tr_status tr_register_noalloc(const float *src, const float *dst, int32_t n, const tr_params *p,
+                              tr_result *out_dev, uint8_t *mask_dev, void *stream);
 
 /* Register B pairs of uneven size in one pass. Pair b owns matches
  * [offsets[b], offsets[b+1]) of src/dst; offsets_dev is B+1 int32 in device

@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -486,6 +487,86 @@ tr_status tr_register(tr_handle *h, const float *src, const float *dst, int32_t 
     st = enqueue(h, w, nullptr, n, 1, n, ev, pmode, false, s, tuning_for(h, n, 1), ev_mask);
     if (st == TR_OK) remember(h, w, 1, s);
     return st;
+}
+
+// ---------------------------------------------------------------- entry point without allocation
+
+// The workspace of tr_register_noalloc: one static array per device, carved by the same layout
+// as a handle's allocations. Host code uses the address hipGetSymbolAddress returns on each
+// device, never this name (which on the host is only a stand-in).
+static __device__ __align__(256) uint8_t scratch[TR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+
+struct NoAllocDevice {
+    bool ready = false;
+    tr_status status = TR_OK;   // of the set-up on this device
+    tr_handle h;                // sizes and the carved workspace (no allocations of its own)
+};
+
+std::mutex g_noalloc_mutex;
+NoAllocDevice g_noalloc[kNoAllocDevices];
+
+// Once per device, with that device current: the array's address there, the workspace carved
+// from it, and the kernel attributes tr_create would set.
+tr_status noalloc_setup(int device, tr_handle &h)
+{
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TR_ERR_HIP;
+    h.device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        h.num_cus = cus;
+    size_handle(&h, TR_NOALLOC_MAX_N, 1, TR_NOALLOC_MAX_K1, TR_MAX_K2);
+    size_t off = 0;
+    bool fits = true;
+    workspace_layout(&h, [&](auto *&q, size_t count) {
+        using T = std::remove_reference_t<decltype(*q)>;
+        off = (off + 255) & ~(size_t)255;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (off + bytes > TR_NOALLOC_SCRATCH_BYTES) {
+            fits = false;
+            q = nullptr;
+            return;
+        }
+        q = reinterpret_cast<T *>(static_cast<uint8_t *>(ptr) + off);
+        off += bytes;
+    });
+    if (!fits) return TR_ERR_WORKSPACE;
+    hipError_t e = setup_graph_kernels();
+    if (e == hipSuccess) e = setup_pivot_kernels();
+    if (e == hipSuccess) e = setup_hyp_kernels();
+    return e == hipSuccess ? TR_OK : TR_ERR_HIP;
+}
+
+}  // namespace
+
+tr_status tr_register_noalloc(const float *src, const float *dst, int32_t n, const tr_params *p,
+                              tr_result *out_dev, uint8_t *mask_dev, void *stream)
+{
+    if (!src || !dst || !out_dev || !p || n < 3) return TR_ERR_INVALID_ARG;
+    if (p->pivot_mode != TR_PIVOTS_PLAIN || (p->flags & (TR_FLAG_PROFILE | TR_FLAG_PROFILE_SC2)))
+        return TR_ERR_INVALID_ARG;
+    if (n > TR_NOALLOC_MAX_N || p->k1 > TR_NOALLOC_MAX_K1) return TR_ERR_WORKSPACE;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess || device < 0 || device >= kNoAllocDevices) return TR_ERR_HIP;
+    NoAllocDevice &d = g_noalloc[device];
+    {
+        std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+        if (!d.ready) {
+            d.status = noalloc_setup(device, d.h);
+            d.ready = true;
+        }
+    }
+    if (d.status != TR_OK) return d.status;
+    tr_status st = check_params(&d.h, p);
+    if (st != TR_OK) return st;
+    Work w = make_work(&d.h, src, dst, *p, out_dev, mask_dev, false, 1, n);
+    w.n1 = n;
+    return enqueue(&d.h, w, nullptr, n, 1, n, nullptr, 0, false, static_cast<hipStream_t>(stream),
+                   tuning_for(&d.h, n, 1));
 }
 
 tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, const int32_t *offsets_dev, int32_t B,

@@ -22,6 +22,8 @@ TR_PIVOTS_PLAIN, TR_PIVOTS_LEARNED = 0, 1
 TR_FLAG_PROFILE, TR_FLAG_PROFILE_SC2, TR_FLAG_RANK_MAE, TR_FLAG_RANK_MSE = 1, 2, 4, 8
 TR_MAX_K2 = 8
 TR_SC2_SPARSE_CAP_MAX = 8192
+TR_NOALLOC_MAX_N = 2048
+TR_NOALLOC_MAX_K1 = 1024
 TR_MLP_NPARAM = 5505
 (TR_TAP_C, TR_TAP_G, TR_TAP_PIVOTS, TR_TAP_CLIQUES, TR_TAP_POSES, TR_TAP_IN, TR_TAP_FEATURES,
  TR_TAP_SCORES, TR_TAP_PLAIN_PIVOTS, TR_TAP_RANK_SCORES) = range(10)
@@ -31,7 +33,8 @@ TR_NUM_STAGES = len(STAGES)
 EXPORTS = ("tr_create", "tr_destroy", "tr_register", "tr_register_batch", "tr_scorer_load",
            "tr_scorer_save", "tr_scorer_set", "tr_scorer_get", "tr_features_batch", "tr_mlp_forward",
            "tr_mlp_grads", "tr_train_step", "tr_debug_copy", "tr_stage_times", "tr_status_string",
-           "tr_tuning_get", "tr_tuning_set", "tr_autotune", "tr_score_poses", "tr_fit_triplets")
+           "tr_tuning_get", "tr_tuning_set", "tr_autotune", "tr_score_poses", "tr_fit_triplets",
+           "tr_register_noalloc")
 
 
 class tr_params(ct.Structure):
@@ -69,6 +72,7 @@ def lib():
         L.tr_destroy.argtypes = [vp]
         L.tr_register.argtypes = [vp, vp, vp, I32, ct.POINTER(tr_params), vp, vp, vp]
         L.tr_register_batch.argtypes = [vp, vp, vp, vp, I32, I32, ct.POINTER(tr_params), vp, vp, vp]
+        L.tr_register_noalloc.argtypes = [vp, vp, I32, ct.POINTER(tr_params), vp, vp, vp]
         L.tr_scorer_load.argtypes = [vp, vp, ct.c_size_t]
         L.tr_scorer_save.argtypes = [vp, vp, ct.c_size_t, ct.POINTER(ct.c_size_t)]
         L.tr_scorer_set.argtypes = [vp, vp]
@@ -149,6 +153,11 @@ def tr_destroy(h):
 def tr_register(h, src, dst, n, params, out, mask=None):
     _ck(lib().tr_register(h, _ptr(src), _ptr(dst), int(n), ct.byref(params), _ptr(out), _ptr(mask), _stream()),
         "tr_register")
+
+
+def tr_register_noalloc(src, dst, n, params, out, mask=None):
+    _ck(lib().tr_register_noalloc(_ptr(src), _ptr(dst), int(n), ct.byref(params), _ptr(out), _ptr(mask), _stream()),
+        "tr_register_noalloc")
 
 
 def tr_register_batch(h, src, dst, offsets, B, max_n, params, out, masks=None):
