@@ -20,6 +20,8 @@ constexpr int kScorePts = 256;    // points per scoring work item (staged in LDS
 constexpr int kCollectRegions = 8; // pivot collection: one pool region and counter per XCD
 constexpr int kHypGroup = 16;     // clique-search items per first-level ticket
 constexpr int kTickLine = 32;     // int32 per counter: one counter per 128-byte line
+constexpr int kTickHyp0 = kCollectRegions;      // first clique-search group ticket
+constexpr int kFusedPool = 512;   // learned pools up to this size are reordered inside the hypothesis kernel
 
 // Work-list stages whose per-pair item counts depend on N_b; each has a
 // prefix array of B+1 entries in Plan::pre.
@@ -109,6 +111,7 @@ struct Work {
     tr_result *out;
     uint8_t *masks;           // nullable; pair b's mask starts at pairs[b].pt_off
     int32_t learned;          // learned pivot mode / feature accumulation on
+    int32_t rank_in_hyp;      // learned pool of at most kFusedPool entries: the hypothesis kernel orders it
     // Profiled calls only (null otherwise): the hypothesis kernel's phase durations in ticks of
     // the 100 MHz real-time clock, per work item (max_batch x rec_stride / 2 x 4: clique search,
     // rigid fits, scoring, records), and their sums over calls (kProfSlots counters).
@@ -130,6 +133,38 @@ __device__ __forceinline__ float length32(float ax, float ay, float az)
     s = __builtin_fmaf(ay, ay, s);
     s = __builtin_fmaf(az, az, s);
     return __builtin_sqrtf(s);
+}
+
+// Learned reorder key of plain pool entry r (smaller = earlier): e = s_i + s_j descending, then
+// the plain rank r; keys are distinct. fb: the pair's scores are not all finite, keep plain order.
+__device__ __forceinline__ uint64_t reorder_key(const int32_t *pl, const float *sc, int r, bool fb)
+{
+    uint32_t hi = 0;
+    if (!fb) {
+        const float e = (sc[pl[3 * r]] + sc[pl[3 * r + 1]]) + 0.0f;   // +0.0f folds -0 into +0
+        const uint32_t u = __float_as_uint(e);
+        const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending float order
+        hi = ~ord;                                                            // descending
+    }
+    return ((uint64_t)hi << 32) | (uint32_t)r;
+}
+
+// Number of the keys in [q0, q1) (LDS, padded with ~0 to a multiple of 16) smaller than `mine`,
+// eight 16-byte broadcast reads in flight; q0, q1 multiples of 16.
+__device__ __forceinline__ int count_smaller(const uint64_t *keys, int q0, int q1, uint64_t mine)
+{
+    int rk = 0;
+    for (int q = q0; q < q1; q += 16) {
+        uint4 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const uint4 *>(&keys[q + 2 * u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            rk += (((uint64_t)a[u].y << 32) | a[u].x) < mine;
+            rk += (((uint64_t)a[u].w << 32) | a[u].z) < mine;
+        }
+    }
+    return rk;
 }
 
 __device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)

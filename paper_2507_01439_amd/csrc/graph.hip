@@ -861,18 +861,45 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                 for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
             }
         }
-        if (LEARNED) {   // column j of the upper tile is row j of the lower one (Ghat is symmetric)
+        if (LEARNED) {
+            // column j of the upper tile is row j of the lower one (Ghat is symmetric): thread t sums
+            // and maximises columns 2c, 2c+1 (c = t mod 128) of the masked tile over rows of parity
+            // t / 128, sixteen 4-byte reads in flight; the two parities meet in LDS
             __syncthreads();
-            const int j = bj * kSc2Tile + tid;
-            int csum = 0, cmax = 0;
-            for (int r = 0; r < kSc2Tile; ++r) {
-                const int v = T[r * kSc2Tile + tid];
-                csum += v;
-                cmax = max(cmax, v);
+            const int cp = tid & 127, par = tid >> 7;
+            const uint32_t *Tw = reinterpret_cast<const uint32_t *>(T);
+            int s0 = 0, s1 = 0;
+            u16x2 mx = {0, 0};
+            for (int m0 = 0; m0 < kSc2Tile / 2; m0 += 16) {
+                uint32_t v[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) v[u] = Tw[(2 * (m0 + u) + par) * (kSc2Tile / 2) + cp];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    s0 += (int)(v[u] & 0xFFFFu);
+                    s1 += (int)(v[u] >> 16);
+                    mx = __builtin_elementwise_max(mx, __builtin_bit_cast(u16x2, v[u]));
+                }
             }
-            if (cmax > 0) {
-                atomicAdd(&rstat[j * 20 + 1], csum);
-                atomicMax(&rstat[j * 20 + 2], cmax);
+            __syncthreads();   // the tile is read
+            int32_t *xl = reinterpret_cast<int32_t *>(smem);
+            if (par) {
+                xl[3 * cp] = s0;
+                xl[3 * cp + 1] = s1;
+                xl[3 * cp + 2] = (int32_t)__builtin_bit_cast(uint32_t, mx);
+            }
+            __syncthreads();
+            if (!par) {
+                const u16x2 m2 = __builtin_elementwise_max(mx, __builtin_bit_cast(u16x2, (uint32_t)xl[3 * cp + 2]));
+                const int cs[2] = {s0 + xl[3 * cp], s1 + xl[3 * cp + 1]}, cm[2] = {(int)m2.x, (int)m2.y};
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    const int j = bj * kSc2Tile + 2 * cp + e;
+                    if (cm[e] > 0) {
+                        atomicAdd(&rstat[j * 20 + 1], cs[e]);
+                        atomicMax(&rstat[j * 20 + 2], cm[e]);
+                    }
+                }
             }
         }
         __syncthreads();

@@ -264,10 +264,10 @@ __device__ __forceinline__ void top_insert(uint32_t (&top)[KMAX], uint32_t k)
 // write them (slot-major); lane s < K2 returns the third vertex of clique s
 // (-1: none), pi / pj the pivot (-1 for an empty slot).
 template <int KMAX>
-__device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, int lane, int &pi, int &pj)
+__device__ int clique_search(const Work &w, const PairDesc &d, int b, int p, const int32_t *pv, int lane, int &pi,
+                             int &pj)
 {
     {
-        const int32_t *pv = w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
         int i = d.n > 0 ? pv[0] : -1, j = d.n > 0 ? pv[1] : -1;
         if (i < 0 || j < 0 || i >= d.n || j >= d.n || i == j) i = j = -1;   // an empty slot (or a bad index) finds no clique
         int32_t *cl = w.cliques + (int64_t)b * w.h_cap * 3;
@@ -590,6 +590,8 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
     __shared__ float sc_l[4][16 * TR_MAX_K2];   // per-wave error-score sums (METRIC only)
     __shared__ uint64_t key_l[NW];
     __shared__ int32_t nv_l[NW], last;
+    __shared__ __attribute__((aligned(16))) uint64_t rkeys[kFusedPool];   // learned pool ordered here
+    __shared__ int32_t piv_l[16][3];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int ipp = (w.k1 + ppw - 1) / ppw, total = B * ipp;
     const float th2 = w.theta * w.theta;
@@ -602,11 +604,38 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
         uint64_t ts0 = 0, ts1 = 0, ts2 = 0, ts3 = 0;
         if (w.hyp_prof) ts0 = ts1 = __builtin_amdgcn_s_memrealtime();
         if (tid < 16 * TR_MAX_K2) tot_l[tid] = 0;
+        if (w.rank_in_hyp) {
+            // learned pivots (pool of K <= kFusedPool plain pivots): the item's ppw positions of the
+            // pool ordered by the learned key, each key ranked against all of the pair's keys
+            const int K = d.kpiv, K16 = (K + 15) & ~15;
+            const bool fb = w.state[b].fallback != 0;
+            const int32_t *pl = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
+            const float *sc = w.scores + (int64_t)b * w.max_n;
+            for (int r = tid; r < K16; r += NT) rkeys[r] = r < K ? reorder_key(pl, sc, r, fb) : ~0ull;
+            if (tid < 3 * ppw) piv_l[tid / 3][tid % 3] = tid % 3 == 2 ? 0 : -1;   // positions past K stay empty
+            __syncthreads();
+            for (int r = tid; r < K; r += NT) {
+                const int rk = count_smaller(rkeys, 0, K16, rkeys[r]), lp = rk - g * ppw;
+                if (lp >= 0 && lp < ppw && rk < w.k1) {
+                    piv_l[lp][0] = pl[3 * r];
+                    piv_l[lp][1] = pl[3 * r + 1];
+                    piv_l[lp][2] = pl[3 * r + 2];
+                }
+            }
+            __syncthreads();
+            if (tid < ppw && g * ppw + tid < w.k1) {   // the ordered list, for inspection
+                int32_t *o = w.pivots + ((int64_t)b * w.piv_stride + g * ppw + tid) * 3;
+                o[0] = piv_l[tid][0];
+                o[1] = piv_l[tid][1];
+                o[2] = piv_l[tid][2];
+            }
+        }
         for (int r = 0; r < (ppw + NW - 1) / NW; ++r) {
             const int lp = r * NW + wv, p = g * ppw + lp;
             if (lp >= ppw) break;   // the same on the whole wave
             int pi = -1, pj = -1, z = -1;
-            if (p < w.k1) z = clique_search<KMAX>(w, d, b, p, lane, pi, pj);
+            const int32_t *pv = w.rank_in_hyp ? &piv_l[lp][0] : w.pivots + ((int64_t)b * w.piv_stride + p) * 3;
+            if (p < w.k1) z = clique_search<KMAX>(w, d, b, p, pv, lane, pi, pj);
             if (w.hyp_prof && tid == 0) ts1 = __builtin_amdgcn_s_memrealtime();
             if (lane < w.k2) {
                 float pose[12];
@@ -731,18 +760,20 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
                 for (int f = 0; f < 4; ++f) __hip_atomic_store(ip + f, dur[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        // every store of this item has been acknowledged before its ticket. Two levels of tickets:
-        // the last item of a group of kHypGroup takes a ticket of the pair, and the workgroup
-        // that takes the pair's last ticket reads the records and the best pose with device-scope
-        // loads (no counter is shared by more than kHypGroup items or ceil(ipp / kHypGroup) groups)
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        // Two levels of tickets: the last item of a group of kHypGroup takes a ticket of the pair,
+        // and the workgroup that takes the pair's last ticket reads the records and the best pose
+        // (no counter is shared by more than kHypGroup items or ceil(ipp / kHypGroup) groups).
+        // The workgroup's stores are ordered before its ticket by the barrier and the ticket's
+        // release at device scope; the last taker's acquire orders its reads after every ticket.
         __syncthreads();
         if (tid == 0) {
             const int grp = g / kHypGroup, ngrp = (ipp + kHypGroup - 1) / kHypGroup;
             const int gsz = min(kHypGroup, ipp - grp * kHypGroup);
-            int32_t *gt = w.tick + (int64_t)b * w.tick_stride + (kCollectRegions + grp) * kTickLine;
-            bool l = atomicAdd(gt, 1) == gsz - 1;
-            if (l) l = atomicAdd(&w.state[b].done, 1) == ngrp - 1;
+            int32_t *gt = w.tick + (int64_t)b * w.tick_stride + (kTickHyp0 + grp) * kTickLine;
+            bool l = __hip_atomic_fetch_add(gt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gsz - 1;
+            if (l)
+                l = __hip_atomic_fetch_add(&w.state[b].done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                    ngrp - 1;
             last = l;
         }
         __syncthreads();

@@ -115,11 +115,15 @@ __device__ __forceinline__ int wave_total(int v)
 }
 
 // The scorer's weights in LDS, unit-minor so that lane o of a wave reads
-// unit o's weight for input k from consecutive words (no bank conflicts).
+// unit o's weight for input k from consecutive words (no bank conflicts); rows
+// padded to 65 words so that the staging writes, which follow the parameters'
+// global (unit-major) order, fall in distinct banks too.
 struct MlpWave {
-    float w1[19][64], w2[64][64], b1[64], b2[64], w3[64], b3;
-    // Thread tid's share of the weights, fetched into registers early and
-    // written to LDS later (put), so that the global reads overlap other work.
+    static constexpr int kPad = 65;
+    float w1[19][kPad], w2[64][kPad], b1[64], b2[64], w3[64], b3;
+    // Thread tid's share of the weights (coalesced loads of the parameter
+    // vector), fetched into registers early and written to LDS later (put), so
+    // that the global reads overlap other work.
     struct Share {
         float a[5], c[16], e[3], f;
     };
@@ -142,12 +146,12 @@ struct MlpWave {
     {
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
-            const int t = tid + 256 * u;
+            const int t = tid + 256 * u;   // W1[o][k], o = t / 19, k = t % 19
             if (t < 19 * 64) w1[t % 19][t / 19] = r.a[u];
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            const int t = tid + 256 * u;
+            const int t = tid + 256 * u;   // W2[o][k], o = t / 64, k = t % 64
             w2[t & 63][t >> 6] = r.c[u];
         }
         if (tid < 64) {
@@ -158,24 +162,34 @@ struct MlpWave {
         if (tid == 0) b3 = r.f;
     }
     // Score of one match by a whole wave: lane o computes hidden unit o, each
-    // layer one multiply-add chain per lane over inputs broadcast with
-    // v_readlane, in the same order as the one-thread forward pass. fb: lane
-    // k < 19 holds feature k (bfloat16 bits).
-    __device__ float score(uint16_t fb, int lane) const
+    // layer one multiply-add chain per lane over inputs broadcast from the
+    // wave's LDS row x (64 floats), in the same order as the one-thread forward
+    // pass. fb: lane k < 19 holds feature k (bfloat16 bits).
+    __device__ float score(uint16_t fb, int lane, float *x) const
     {
+        auto publish = [&](float v) {   // every lane's value to x, visible to the whole wave
+            x[lane] = v;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        publish(lane < 19 ? bf2f(fb) : 0.0f);
         float acc = b1[lane];
 #pragma unroll
-        for (int k = 0; k < 19; ++k)
-            acc = __builtin_fmaf(w1[k][lane], bf2f((uint16_t)__builtin_amdgcn_readlane((int)fb, k)), acc);
+        for (int k = 0; k < 19; ++k) acc = __builtin_fmaf(w1[k][lane], x[k], acc);
         const float a1 = bfround(gelu(acc));
+        __builtin_amdgcn_wave_barrier();   // every lane has read the features
+        publish(a1);
         acc = b2[lane];
 #pragma unroll
-        for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(w2[k][lane], lane_f(a1, k), acc);
+        for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(w2[k][lane], x[k], acc);
         const float a2 = bfround(gelu(acc));
-        const float w3l = w3[lane];
+        __builtin_amdgcn_wave_barrier();
+        publish(a2);
         float s = b3;
 #pragma unroll
-        for (int o = 0; o < 64; ++o) s = __builtin_fmaf(lane_f(w3l, o), lane_f(a2, o), s);
+        for (int o = 0; o < 64; ++o) s = __builtin_fmaf(w3[o], x[o], s);
+        __builtin_amdgcn_wave_barrier();   // x is free for the wave's next row
         return s;
     }
 };
@@ -189,6 +203,24 @@ __device__ __forceinline__ uint16_t feature_bits(int32_t v, int k, int n)
 
 constexpr int kCandRows = 4;   // rows evaluated together against each loaded point
 
+// Pool entry r moves to slot rk (kept if rk < K1); slots past the pair's K pivots are empty.
+__device__ __forceinline__ void place_pivot(const Work &w, int b, int K, int p, uint64_t mine, int rk)
+{
+    const int32_t *pl = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
+    int32_t *out = w.pivots + (int64_t)b * w.piv_stride * 3;
+    if (p < K && rk < w.k1) {
+        const int r = (int)(uint32_t)mine;
+        out[3 * rk] = pl[3 * r];
+        out[3 * rk + 1] = pl[3 * r + 1];
+        out[3 * rk + 2] = pl[3 * r + 2];
+    }
+    if (p >= K && p < w.k1) {
+        out[3 * p] = -1;
+        out[3 * p + 1] = -1;
+        out[3 * p + 2] = 0;
+    }
+}
+
 // Features and score of every match the reorder needs: the endpoints of the
 // pair's plain pivot pool. The endpoints are cut into chunks of R (at most
 // kCandRows); wave 0 claims each distinct row of its chunk by compare-and-swap
@@ -196,143 +228,183 @@ constexpr int kCandRows = 4;   // rows evaluated together against each loaded po
 // each of the pair's points once and evaluates delta_ij against all claimed
 // rows, exactly as the compatibility kernel does (same operation order,
 // correctly rounded square roots), counting the degree and the 16-bin delta
-// histogram; the SC2 row sum and maximum come from the SC2 epilogue. Each wave
-// then scores the rows of its slot. Matches outside the pool get no features
-// and no score.
+// histogram; the SC2 row sum and maximum come from the SC2 epilogue (loaded at
+// the claim, in flight during the point loop). Each wave then scores the rows
+// of its slot. Matches outside the pool get no features and no score.
+//
 __global__ void __launch_bounds__(256) k_cand_rows(Work w, int B, int R, const uint16_t *wbf16, const float *w32)
 {
     __shared__ float crd[kCandRows][6];
-    __shared__ int32_t row_l[kCandRows];
+    __shared__ int32_t row_l[kCandRows], rsv_l[kCandRows][2];
     __shared__ int32_t cnt_l;
     __shared__ int32_t red[4][kCandRows][9];
     __shared__ MlpWave mlp;
+    __shared__ float act_l[4][64];   // per-wave broadcast row of the scorer
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const MlpWave::Share share = MlpWave::fetch(wbf16, w32, tid);
-    bool staged = false;   // weights written to LDS (before the first scoring)
+    {   // the weights go to LDS while the first chunk's loads are in flight (first barrier below)
+        const MlpWave::Share share = MlpWave::fetch(wbf16, w32, tid);
+        mlp.put(share, tid);
+    }
     const float tau = w.tau, q = tau * 0.25f;
     float edge[16];
 #pragma unroll
     for (int k = 1; k < 16; ++k) edge[k] = (float)k * q;   // bin edges as the compatibility kernel forms them
+    // Fast bin decision: t = delta / q in float32 is within 2^-22 t of the quotient and v_sqrt_f32
+    // moves delta by at most 2^-21 (|x| + |y|); away from every edge by the guard band
+    // 2^-19 (|x| + |y|) + 2e-6 + 2^-17 q, floor(t) is the bin and delta <= tau is decided.
+    const float inv_q = 1.0f / q, guard0 = __builtin_fmaf(q, 0x1p-17f, 2e-6f);
     const int cpp = (2 * w.pool + R - 1) / R, total = B * cpp;
     for (int c = blockIdx.x; c < total; c += gridDim.x) {
         const int b = c / cpp, e0 = (c - b * cpp) * R;
         const PairDesc d = pair_desc(w, b);
-        if (e0 >= 2 * d.kpiv) continue;   // same for the whole workgroup
-        // The first batch of points is fetched before the rows are claimed.
-        constexpr int kU = 8;   // point loads in flight per thread
-        float p[kU][6];
-        auto fetch_points = [&](int j0) {
+        if (e0 < 2 * d.kpiv) {   // the same for the whole workgroup
+            // Two batches of kU points per thread are in flight before the rows are claimed
+            // (N <= 4096 takes one round trip); later batches are fetched into the buffer
+            // just consumed while the other one is evaluated.
+            constexpr int kU = 8;
+            float pa[kU][6], pb[kU][6];
+            auto fetch_points = [&](float (&p)[kU][6], int j0) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int64_t gj = d.pt_off + min(j0 + 256 * u, d.n - 1);
-                const float3 a = *reinterpret_cast<const float3 *>(w.src + 3 * gj);   // one 12-byte load
-                const float3 c = *reinterpret_cast<const float3 *>(w.dst + 3 * gj);
-                p[u][0] = a.x; p[u][1] = a.y; p[u][2] = a.z;
-                p[u][3] = c.x; p[u][4] = c.y; p[u][5] = c.z;
+                for (int u = 0; u < kU; ++u) {
+                    const int64_t gj = d.pt_off + min(j0 + 256 * u, d.n - 1);
+                    const float3 a = *reinterpret_cast<const float3 *>(w.src + 3 * gj);   // one 12-byte load
+                    const float3 cc = *reinterpret_cast<const float3 *>(w.dst + 3 * gj);
+                    p[u][0] = a.x; p[u][1] = a.y; p[u][2] = a.z;
+                    p[u][3] = cc.x; p[u][4] = cc.y; p[u][5] = cc.z;
+                }
+            };
+            fetch_points(pa, tid);
+            if (256 * kU < d.n) fetch_points(pb, tid + 256 * kU);
+            int rsum = 0, rmax = 0, pos = -1;   // wave 0: the SC2 row statistics of its claimed row
+            if (wv == 0) {
+                const int e = e0 + lane;
+                int i = -1;
+                if (lane < R && e < 2 * d.kpiv) {
+                    i = w.pivots_plain[((int64_t)b * w.pool_cap + (e >> 1)) * 3 + (e & 1)];
+                    if (i < 0 || i >= d.n || atomicCAS(&w.mark[(int64_t)b * w.max_n + i], 0, 1) != 0) i = -1;
+                }
+                const uint64_t m = __ballot(i >= 0);
+                if (i >= 0) {
+                    pos = __popcll(m & ((1ull << lane) - 1ull));
+                    const int64_t gi = d.pt_off + i;
+                    const int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+                    rsum = rs[1];
+                    rmax = rs[2];
+                    row_l[pos] = i;
+                    crd[pos][0] = w.src[3 * gi]; crd[pos][1] = w.src[3 * gi + 1]; crd[pos][2] = w.src[3 * gi + 2];
+                    crd[pos][3] = w.dst[3 * gi]; crd[pos][4] = w.dst[3 * gi + 1]; crd[pos][5] = w.dst[3 * gi + 2];
+                }
+                if (lane == 0) cnt_l = __popcll(m);
             }
-        };
-        fetch_points(tid);
-        if (wv == 0) {
-            const int e = e0 + lane;
-            int i = -1;
-            if (lane < R && e < 2 * d.kpiv) {
-                i = w.pivots_plain[((int64_t)b * w.pool_cap + (e >> 1)) * 3 + (e & 1)];
-                if (i < 0 || i >= d.n || atomicCAS(&w.mark[(int64_t)b * w.max_n + i], 0, 1) != 0) i = -1;
-            }
-            const uint64_t m = __ballot(i >= 0);
-            if (i >= 0) {
-                const int pos = __popcll(m & ((1ull << lane) - 1ull));
-                const int64_t gi = d.pt_off + i;
-                row_l[pos] = i;
-                crd[pos][0] = w.src[3 * gi]; crd[pos][1] = w.src[3 * gi + 1]; crd[pos][2] = w.src[3 * gi + 2];
-                crd[pos][3] = w.dst[3 * gi]; crd[pos][4] = w.dst[3 * gi + 1]; crd[pos][5] = w.dst[3 * gi + 2];
-            }
-            if (lane == 0) cnt_l = __popcll(m);
-        }
-        __syncthreads();
-        const int cnt = cnt_l;
-        if (cnt == 0) {
-            __syncthreads();   // cnt_l is the next chunk's
-            continue;
-        }
-        uint32_t cw[kCandRows][4];   // 16 bins, 8 bits each (at most ceil(32767/256) per thread)
-        int deg[kCandRows];
+            __syncthreads();
+            const int cnt = cnt_l;
+            if (cnt > 0) {   // the same for the whole workgroup
+                uint32_t cw[kCandRows][4];   // 16 bins, 8 bits each (at most ceil(32767/256) per thread)
+                int deg[kCandRows];
 #pragma unroll
-        for (int r = 0; r < kCandRows; ++r) {
-            deg[r] = 0;
-            cw[r][0] = cw[r][1] = cw[r][2] = cw[r][3] = 0;
-        }
-        for (int j0 = tid; j0 < d.n; j0 += 256 * kU) {
+                for (int r = 0; r < kCandRows; ++r) {
+                    deg[r] = 0;
+                    cw[r][0] = cw[r][1] = cw[r][2] = cw[r][3] = 0;
+                }
+                auto eval_points = [&](float (&p)[kU][6], int j0) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                const int j = j0 + 256 * u;
+                    for (int u = 0; u < kU; ++u) {
+                        const int j = j0 + 256 * u;
+#pragma unroll
+                        for (int r = 0; r < kCandRows; ++r) {
+                            if (r >= cnt) break;
+                            // hardware square roots first; a pair whose delta lies within the guard
+                            // band of a bin edge k q (tau = 4 q is edge 4) is evaluated again with
+                            // the correctly rounded ones, so every decision is the exact one
+                            const float ax = crd[r][0] - p[u][0], ay = crd[r][1] - p[u][1], az = crd[r][2] - p[u][2];
+                            const float bx = crd[r][3] - p[u][3], by = crd[r][4] - p[u][4], bz = crd[r][5] - p[u][5];
+                            float s1 = ax * ax, s2 = bx * bx;
+                            s1 = __builtin_fmaf(ay, ay, s1);
+                            s2 = __builtin_fmaf(by, by, s2);
+                            s1 = __builtin_fmaf(az, az, s1);
+                            s2 = __builtin_fmaf(bz, bz, s2);
+                            const float la = __builtin_amdgcn_sqrtf(s1), lb = __builtin_amdgcn_sqrtf(s2);
+                            float dl = __builtin_fabsf(la - lb);
+                            const float t = dl * inv_q;
+                            const float kn = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(t), 1.0f), 15.0f);
+                            const float guard = __builtin_fmaf(la + lb, 0x1p-19f, guard0);
+                            int bin;
+                            if (__builtin_fabsf(dl - kn * q) <= guard || !(dl == dl)) {
+                                const float lx = length32(ax, ay, az), ly = length32(bx, by, bz);
+                                dl = __builtin_fabsf(lx - ly);
+                                bin = 0;
+#pragma unroll
+                                for (int k = 1; k < 16; ++k) bin += dl >= edge[k];
+                            } else {
+                                bin = (int)__builtin_fminf(t, 15.0f);   // t >= 0, at least the guard from an integer
+                            }
+                            const bool in = j < d.n && j != row_l[r];
+                            deg[r] += in && dl <= tau;
+                            const uint32_t inc = in ? 1u << (8 * (bin & 3)) : 0u;
+                            cw[r][0] += (bin >> 2) == 0 ? inc : 0u;
+                            cw[r][1] += (bin >> 2) == 1 ? inc : 0u;
+                            cw[r][2] += (bin >> 2) == 2 ? inc : 0u;
+                            cw[r][3] += (bin >> 2) == 3 ? inc : 0u;
+                        }
+                    }
+                };
+                for (int j0 = tid; j0 < d.n; j0 += 2 * 256 * kU) {
+                    eval_points(pa, j0);
+                    if (j0 + 2 * 256 * kU < d.n) fetch_points(pa, j0 + 2 * 256 * kU);
+                    if (j0 + 256 * kU < d.n) eval_points(pb, j0 + 256 * kU);
+                    if (j0 + 3 * 256 * kU < d.n) fetch_points(pb, j0 + 3 * 256 * kU);
+                }
+                // Per row: bytes 0,2 and 1,3 of each counter word widen to 16-bit
+                // fields (a workgroup's count of one bin is below 2^15).
 #pragma unroll
                 for (int r = 0; r < kCandRows; ++r) {
                     if (r >= cnt) break;
-                    const float lx = length32(crd[r][0] - p[u][0], crd[r][1] - p[u][1], crd[r][2] - p[u][2]);
-                    const float ly = length32(crd[r][3] - p[u][3], crd[r][4] - p[u][4], crd[r][5] - p[u][5]);
-                    const float dl = __builtin_fabsf(lx - ly);
-                    const bool in = j < d.n && j != row_l[r];
-                    deg[r] += in && dl <= tau;
-                    int bin = 0;
 #pragma unroll
-                    for (int k = 1; k < 16; ++k) bin += dl >= edge[k];
-                    const uint32_t inc = in ? 1u << (8 * (bin & 3)) : 0u;
-                    cw[r][0] += (bin >> 2) == 0 ? inc : 0u;
-                    cw[r][1] += (bin >> 2) == 1 ? inc : 0u;
-                    cw[r][2] += (bin >> 2) == 2 ? inc : 0u;
-                    cw[r][3] += (bin >> 2) == 3 ? inc : 0u;
+                    for (int m = 0; m < 4; ++m) {
+                        const int te = wave_total((int)(cw[r][m] & 0x00FF00FFu));
+                        const int to = wave_total((int)((cw[r][m] >> 8) & 0x00FF00FFu));
+                        if (lane == 0) {
+                            red[wv][r][2 * m] = te;
+                            red[wv][r][2 * m + 1] = to;
+                        }
+                    }
+                    const int td = wave_total(deg[r]);
+                    if (lane == 0) red[wv][r][8] = td;
                 }
-            }
-            if (j0 + 256 * kU < d.n) fetch_points(j0 + 256 * kU);
-        }
-        // Per row: bytes 0,2 and 1,3 of each counter word widen to 16-bit
-        // fields (a workgroup's count of one bin is below 2^15).
-#pragma unroll
-        for (int r = 0; r < kCandRows; ++r) {
-            if (r >= cnt) break;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int te = wave_total((int)(cw[r][m] & 0x00FF00FFu));
-                const int to = wave_total((int)((cw[r][m] >> 8) & 0x00FF00FFu));
-                if (lane == 0) {
-                    red[wv][r][2 * m] = te;
-                    red[wv][r][2 * m + 1] = to;
+                if (pos >= 0) {
+                    rsv_l[pos][0] = rsum;
+                    rsv_l[pos][1] = rmax;
                 }
-            }
-            const int td = wave_total(deg[r]);
-            if (lane == 0) red[wv][r][8] = td;
-        }
-        if (!staged) mlp.put(share, tid);
-        staged = true;
-        __syncthreads();
+                __syncthreads();
 #pragma unroll 1
-        for (int r = wv; r < cnt; r += 4) {
-            const int i = row_l[r];
-            int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
-            int32_t v = 0;
-            if (lane == 0) {
-                v = red[0][r][8] + red[1][r][8] + red[2][r][8] + red[3][r][8];
-            } else if (lane < 3) {
-                v = rs[lane];   // SC2 row sum / maximum
-            } else if (lane < 19) {
-                const int bin = lane - 3, idx = 2 * (bin >> 2) + (bin & 1), sh = 16 * ((bin >> 1) & 1);
+                for (int r = wv; r < cnt; r += 4) {
+                    const int i = row_l[r];
+                    int32_t *rs = w.rowstat + ((int64_t)b * w.max_n + i) * 20;
+                    int32_t v = 0;
+                    if (lane == 0) {
+                        v = red[0][r][8] + red[1][r][8] + red[2][r][8] + red[3][r][8];
+                    } else if (lane < 3) {
+                        v = rsv_l[r][lane - 1];   // SC2 row sum / maximum
+                    } else if (lane < 19) {
+                        const int bin = lane - 3, idx = 2 * (bin >> 2) + (bin & 1), sh = 16 * ((bin >> 1) & 1);
 #pragma unroll
-                for (int g = 0; g < 4; ++g) v += (red[g][r][idx] >> sh) & 0xFFFF;
-            }
-            uint16_t fb = 0;
-            if (lane < 19) {
-                if (lane == 0 || lane >= 3) rs[lane] = v;
-                fb = feature_bits(v, lane, d.n);
-                w.feat[((int64_t)b * w.max_n + i) * 19 + lane] = fb;
-            }
-            const float sc = mlp.score(fb, lane);
-            if (lane == 0) {
-                w.scores[(int64_t)b * w.max_n + i] = sc;
-                if (!isfinite(sc)) atomicOr(&w.state[b].fallback, 1);
+                        for (int g = 0; g < 4; ++g) v += (red[g][r][idx] >> sh) & 0xFFFF;
+                    }
+                    uint16_t fb = 0;
+                    if (lane < 19) {
+                        if (lane == 0 || lane >= 3) rs[lane] = v;
+                        fb = feature_bits(v, lane, d.n);
+                        w.feat[((int64_t)b * w.max_n + i) * 19 + lane] = fb;
+                    }
+                    const float sc = mlp.score(fb, lane, act_l[wv]);
+                    if (lane == 0) {
+                        w.scores[(int64_t)b * w.max_n + i] = sc;
+                        if (!isfinite(sc)) atomicOr(&w.state[b].fallback, 1);
+                    }
+                }
             }
         }
-        __syncthreads();   // row_l, crd, red and cnt_l are the next chunk's
+        __syncthreads();   // row_l, crd, red, rsv_l and cnt_l are the next chunk's
     }
 }
 
@@ -341,7 +413,8 @@ __global__ void __launch_bounds__(256) k_cand_rows(Work w, int B, int R, const u
 // Keys are distinct (the plain rank is part of each), so a key's new position
 // is the number of smaller keys: each 256-thread workgroup rebuilds the
 // pair's K keys in LDS and ranks 64 of them, a quarter of the list per wave,
-// eight 16-byte broadcast reads in flight.
+// eight 16-byte broadcast reads in flight. (Pools larger than kFusedPool; the hypothesis
+// kernel orders smaller ones.)
 __global__ void __launch_bounds__(256) k_reorder(Work w, int blocks_per_pair)
 {
     extern __shared__ uint64_t keys[];
@@ -355,52 +428,17 @@ __global__ void __launch_bounds__(256) k_reorder(Work w, int blocks_per_pair)
     const int32_t *pl = w.pivots_plain + (int64_t)b * w.pool_cap * 3;
     const float *sc = w.scores + (int64_t)b * w.max_n;
     const int K16 = (K + 15) & ~15;
-    for (int r = tid; r < K16; r += 256) {
-        uint64_t k = ~0ull;
-        if (r < K) {
-            uint32_t hi = 0;
-            if (!fb) {
-                const float e = (sc[pl[3 * r]] + sc[pl[3 * r + 1]]) + 0.0f;   // +0.0f folds -0 into +0
-                const uint32_t u = __float_as_uint(e);
-                const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);   // ascending float order
-                hi = ~ord;                                                            // descending
-            }
-            k = ((uint64_t)hi << 32) | (uint32_t)r;
-        }
-        keys[r] = k;
-    }
+    for (int r = tid; r < K16; r += 256) keys[r] = r < K ? reorder_key(pl, sc, r, fb) : ~0ull;
     __syncthreads();
     const int p = g * 64 + lane;
     const uint64_t mine = p < K ? keys[p] : 0;
     const int per = ((K16 / 16 + 3) / 4) * 16;
     const int q0 = min(K16, wv * per), q1 = min(K16, q0 + per);
-    int rk = 0;
-    for (int q = q0; q < q1; q += 16) {
-        uint4 a[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = *reinterpret_cast<const uint4 *>(&keys[q + 2 * u]);
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            rk += (((uint64_t)a[u].y << 32) | a[u].x) < mine;
-            rk += (((uint64_t)a[u].w << 32) | a[u].z) < mine;
-        }
-    }
-    part[wv][lane] = rk;
+    part[wv][lane] = count_smaller(keys, q0, q1, mine);
     __syncthreads();
     if (wv != 0) return;
-    rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-    int32_t *out = w.pivots + (int64_t)b * w.piv_stride * 3;
-    if (p < K && rk < w.k1) {
-        const int r = (int)(uint32_t)mine;
-        out[3 * rk] = pl[3 * r];
-        out[3 * rk + 1] = pl[3 * r + 1];
-        out[3 * rk + 2] = pl[3 * r + 2];
-    }
-    if (p >= K && p < w.k1) {   // slots past the pair's pivots
-        out[3 * p] = -1;
-        out[3 * p + 1] = -1;
-        out[3 * p + 2] = 0;
-    }
+    const int rk = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    place_pivot(w, b, K, p, mine, rk);
 }
 
 // ---------------------------------------------------------------- standalone forward
@@ -716,9 +754,11 @@ hipError_t launch_learned_order(const Work &w, const MlpState &mlp, int B, int g
     const int R = max(1, min(kCandRows, (cand + 2 * grid - 1) / (2 * grid)));
     const int chunks = B * ((2 * w.pool + R - 1) / R);
     hipLaunchKernelGGL(k_cand_rows, dim3(min(chunks, grid * 2)), dim3(256), 0, st, w, B, R, mlp.wbf16, mlp.w32);
-    const int bpp = (max(w.pool, w.k1) + 63) / 64;
-    hipLaunchKernelGGL(k_reorder, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), st, w,
-                       bpp);
+    if (!w.rank_in_hyp) {   // small pools are ordered by the hypothesis kernel itself
+        const int bpp = (max(w.pool, w.k1) + 63) / 64;
+        hipLaunchKernelGGL(k_reorder, dim3(B * bpp), dim3(256), (size_t)((w.pool + 15) & ~15) * sizeof(uint64_t), st,
+                           w, bpp);
+    }
     return hipGetLastError();
 }
 

@@ -125,7 +125,7 @@ void size_handle(tr_handle *h, int32_t max_n, int32_t max_batch, int32_t max_k1,
     h->nblk_stride = (max_n + kRowsPerItem - 1) / kRowsPerItem;
     const int items = (max_k1 + 3) / 4;   // clique-search work items of a pair (at least 4 pivots each)
     h->rec_stride = 2 * items;
-    h->tick_stride = (kCollectRegions + (items + kHypGroup - 1) / kHypGroup) * kTickLine;
+    h->tick_stride = (kTickHyp0 + (items + kHypGroup - 1) / kHypGroup) * kTickLine;
     h->pre_stride = max_batch + 1;
 }
 
@@ -255,6 +255,7 @@ Work make_work(tr_handle *h, const float *src, const float *dst, const tr_params
     w.out = out;
     w.masks = masks;
     w.learned = learned ? 1 : 0;
+    w.rank_in_hyp = learned && w.pool <= kFusedPool ? 1 : 0;
     return w;
 }
 
