@@ -62,6 +62,40 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host AddressSanitizer build (tests only): the same sources with the host side of every
+# translation unit instrumented (-Xarch_host puts the sanitizer on the host pass alone; the GPU
+# code is built as for the library), linked with the host-code driver into one executable.
+ASAN_DIR = os.path.join(HERE, "_build_asan")
+ASAN_DRIVER = os.path.join(os.path.dirname(HERE), "tests", "asan", "host_driver.cpp")
+ASAN_EXE = os.path.join(ASAN_DIR, "host_driver")
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+
+def build_asan(verbose: bool = False) -> str:
+    os.makedirs(ASAN_DIR, exist_ok=True)
+
+    def one(src):
+        obj = os.path.join(ASAN_DIR, os.path.basename(src) + ".o")
+        r = subprocess.run([hipcc(), *FLAGS, *ASAN_FLAGS, "-x", "hip", "-c", src, "-o", obj],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc (host ASan) failed on {src}:\n{r.stderr}")
+        return obj
+
+    srcs = sources() + [ASAN_DRIVER]
+    with cf.ThreadPoolExecutor(max_workers=min(len(srcs), 8)) as ex:
+        objs = list(ex.map(one, srcs))
+    tmp = ASAN_EXE + ".tmp"
+    r = subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address", "-o", tmp, *objs],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (host ASan) failed:\n{r.stderr}")
+    os.replace(tmp, ASAN_EXE)
+    if verbose:
+        print(f"built {ASAN_EXE}")
+    return ASAN_EXE
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
