@@ -182,6 +182,19 @@ tr_status tr_tuning_get(tr_handle *h, int32_t max_n, int32_t B, tr_tuning *out);
  * field is outside its range. Later calls of that group use it (batches on a
  * stream capture a new hipGraph for it). */
 tr_status tr_tuning_set(tr_handle *h, int32_t max_n, int32_t B, const tr_tuning *t);
+/* Persist the launch configurations of a handle: tr_tuning_save writes every
+ * group the handle holds (tuned or set) to a text file: a header line
+ * "turboreg-tuning <version> <gcn arch name> <CU count>", then one line per group
+ * "<256-row tiles> <B> <sc2_super> <compat_per_cu> <hyp_ppw> <hyp_per_cu>
+ * <sc2_sparse_cap>". tr_tuning_load reads such a file into the handle, replacing
+ * the groups it names; a file of another version, architecture or CU count, or
+ * with a malformed or out-of-range line, is refused (TR_ERR_INVALID_ARG) and
+ * changes nothing. I/O failures are TR_ERR_INVALID_ARG too. tr_create loads the
+ * file named by the environment variable TURBOREG_TUNING_CACHE when it is set
+ * and readable (a refused file is ignored there). */
+tr_status tr_tuning_save(tr_handle *h, const char *path);
+tr_status tr_tuning_load(tr_handle *h, const char *path);
+
 /* Autotuner: runs the registration of the given inputs (one pair of N = max_n
  * if offsets_dev is NULL and B == 1, else the batch as tr_register_batch) under
  * candidate configurations, one field at a time starting from the group's

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -37,6 +38,7 @@ struct GraphKey {
 struct tr_handle {
     int device = 0;
     int num_cus = 256;
+    char arch[64] = "unknown";   // gcnArchName of the device (tuning files are per architecture and CU count)
     int32_t max_n = 0, max_batch = 0, max_k1 = 0, max_k2 = 0;
     int32_t npad_max = 0, pool_cap = 0, k1_cap = 0, h_cap = 0, nblk_stride = 0, pre_stride = 0;
     // workspace
@@ -436,7 +438,12 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
     if (!h) return TR_ERR_HIP;
     h->device = device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cus = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        h->num_cus = prop.multiProcessorCount;
+        std::snprintf(h->arch, sizeof(h->arch), "%s", prop.gcnArchName);
+        for (char *c = h->arch; *c; ++c)
+            if (*c == ' ') *c = '_';
+    }
     size_handle(h, max_n, max_batch, max_k1, max_k2);
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t x) {
@@ -455,6 +462,7 @@ tr_status tr_create(tr_handle **out, int32_t max_n, int32_t max_batch, int32_t m
         delete h;
         return TR_ERR_HIP;
     }
+    if (const char *cache = std::getenv("TURBOREG_TUNING_CACHE")) tr_tuning_load(h, cache);   // refused: ignored
     *out = h;
     return TR_OK;
 }
@@ -662,6 +670,50 @@ tr_status tr_tuning_set(tr_handle *h, int32_t max_n, int32_t B, const tr_tuning 
 {
     if (!h || !t || max_n < 3 || B < 1 || !tuning_valid(*t)) return TR_ERR_INVALID_ARG;
     h->tuning[tuning_key(max_n, B)] = *t;
+    return TR_OK;
+}
+
+namespace {
+constexpr int kTuningFileVersion = 1;
+}
+
+tr_status tr_tuning_save(tr_handle *h, const char *path)
+{
+    if (!h || !path) return TR_ERR_INVALID_ARG;
+    std::FILE *f = std::fopen(path, "w");
+    if (!f) return TR_ERR_INVALID_ARG;
+    bool ok = std::fprintf(f, "turboreg-tuning %d %s %d\n", kTuningFileVersion, h->arch, h->num_cus) > 0;
+    for (const auto &g : h->tuning) {
+        const tr_tuning &t = g.second;
+        ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d\n", g.first.first, g.first.second, t.sc2_super,
+                                t.compat_per_cu, t.hyp_ppw, t.hyp_per_cu, t.sc2_sparse_cap) > 0;
+    }
+    ok = std::fclose(f) == 0 && ok;
+    return ok ? TR_OK : TR_ERR_INVALID_ARG;
+}
+
+tr_status tr_tuning_load(tr_handle *h, const char *path)
+{
+    if (!h || !path) return TR_ERR_INVALID_ARG;
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return TR_ERR_INVALID_ARG;
+    char arch[64] = {0};
+    int version = 0, cus = 0;
+    bool ok = std::fscanf(f, "turboreg-tuning %d %63s %d", &version, arch, &cus) == 3 &&
+              version == kTuningFileVersion && std::strcmp(arch, h->arch) == 0 && cus == h->num_cus;
+    std::map<std::pair<int32_t, int32_t>, tr_tuning> read;
+    while (ok) {
+        int tiles = 0, B = 0;
+        tr_tuning t{};
+        const int k = std::fscanf(f, "%d %d %d %d %d %d %d", &tiles, &B, &t.sc2_super, &t.compat_per_cu, &t.hyp_ppw,
+                                  &t.hyp_per_cu, &t.sc2_sparse_cap);
+        if (k == EOF) break;
+        ok = k == 7 && tiles >= 1 && B >= 1 && tuning_valid(t);
+        if (ok) read[{tiles, B}] = t;
+    }
+    std::fclose(f);
+    if (!ok) return TR_ERR_INVALID_ARG;
+    for (const auto &g : read) h->tuning[g.first] = g.second;
     return TR_OK;
 }
 

@@ -34,7 +34,7 @@ EXPORTS = ("tr_create", "tr_destroy", "tr_register", "tr_register_batch", "tr_sc
            "tr_scorer_save", "tr_scorer_set", "tr_scorer_get", "tr_features_batch", "tr_mlp_forward",
            "tr_mlp_grads", "tr_train_step", "tr_debug_copy", "tr_stage_times", "tr_status_string",
            "tr_tuning_get", "tr_tuning_set", "tr_autotune", "tr_score_poses", "tr_fit_triplets",
-           "tr_register_noalloc")
+           "tr_register_noalloc", "tr_tuning_save", "tr_tuning_load")
 
 
 class tr_params(ct.Structure):
@@ -87,6 +87,8 @@ def lib():
         L.tr_fit_triplets.argtypes = [vp, vp, vp, I32, vp, I32, vp, vp, vp]
         L.tr_tuning_get.argtypes = [vp, I32, I32, ct.POINTER(tr_tuning)]
         L.tr_tuning_set.argtypes = [vp, I32, I32, ct.POINTER(tr_tuning)]
+        L.tr_tuning_save.argtypes = [vp, ct.c_char_p]
+        L.tr_tuning_load.argtypes = [vp, ct.c_char_p]
         L.tr_autotune.argtypes = [vp, vp, vp, vp, I32, I32, ct.POINTER(tr_params), vp, vp, vp,
                                   ct.POINTER(tr_tuning), ct.POINTER(ct.c_float)]
         L.tr_status_string.argtypes = [I32]
@@ -183,6 +185,14 @@ def tr_tuning_get(h, max_n, B=1) -> tr_tuning:
 
 def tr_tuning_set(h, max_n, B, t: tr_tuning):
     _ck(lib().tr_tuning_set(h, int(max_n), int(B), ct.byref(t)), "tr_tuning_set")
+
+
+def tr_tuning_save(h, path):
+    _ck(lib().tr_tuning_save(h, os.fsencode(path)), "tr_tuning_save")
+
+
+def tr_tuning_load(h, path):
+    _ck(lib().tr_tuning_load(h, os.fsencode(path)), "tr_tuning_load")
 
 
 def tr_autotune(h, src, dst, offsets, B, max_n, params, out, masks=None):

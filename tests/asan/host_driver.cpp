@@ -86,6 +86,8 @@ void without_device()
     expect_status(tr_register_noalloc(x, x, 10, &big, (tr_result *)x, nullptr, nullptr), TR_ERR_WORKSPACE,
                   "noalloc(k1)");
     expect_status(tr_scorer_load(nullptr, x, sizeof(x)), TR_ERR_INVALID_ARG, "scorer_load(null)");
+    expect_status(tr_tuning_load(nullptr, "x"), TR_ERR_INVALID_ARG, "tuning_load(null)");
+    expect_status(tr_tuning_save(nullptr, "x"), TR_ERR_INVALID_ARG, "tuning_save(null)");
     for (int s = -1; s < 12; ++s) expect(tr_status_string((tr_status)s) != nullptr, "status string");
 }
 
@@ -143,6 +145,11 @@ void with_device()
     expect_status(tr_tuning_set(h, n, 1, &t), TR_ERR_INVALID_ARG, "tuning_set(ppw 5)");
     float ms = 0;
     expect_status(tr_autotune(h, src, dst, nullptr, 1, n, &p, out, mask, nullptr, &t, &ms), TR_OK, "tr_autotune");
+    const char *cache = "asan_tuning_cache.txt";
+    expect_status(tr_tuning_save(h, cache), TR_OK, "tr_tuning_save");
+    expect_status(tr_tuning_load(h, cache), TR_OK, "tr_tuning_load");
+    expect_status(tr_tuning_load(h, "/nonexistent/tuning.txt"), TR_ERR_INVALID_ARG, "tuning_load(missing)");
+    std::remove(cache);
     // the scorer: set, save, load (and a corrupted blob), learned registration
     std::vector<float> w(TR_MLP_NPARAM);
     for (int k = 0; k < TR_MLP_NPARAM; ++k) w[k] = 0.01f * (float)((k * 37) % 19 - 9);

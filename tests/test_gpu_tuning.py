@@ -147,3 +147,59 @@ def test_autotune_batch(reg):
     assert bytes(T.tr_tuning_get(reg.h, max_n, B)) == bytes(best)
     with pytest.raises(T.TurboRegError):
         T.tr_autotune(reg.h, src, dst, None, 2, max_n, prm, out, masks)   # several pairs need offsets
+
+
+def test_tuning_cache_roundtrip(reg, tmp_path):
+    """Tuned configurations persist: a saved file loaded into a new handle (explicitly, and by
+    tr_create through TURBOREG_TUNING_CACHE) gives the same configuration and the same bits;
+    files of another version, architecture, CU count or with a bad line are refused."""
+    import os
+    c = synth.CONFIGS["indoor_n1000"].replace(n=1500, k1=300)
+    p = synth.make_pair(c, synth.pair_seed(6, 30))
+    prm = T.params_from_config(c)
+    src, dst = to_dev(torch, p.src), to_dev(torch, p.dst)
+    out = torch.empty(80, dtype=torch.uint8, device="cuda")
+    mask = torch.empty(c.n, dtype=torch.uint8, device="cuda")
+    best, _ = T.tr_autotune(reg.h, src, dst, None, 1, c.n, prm, out, mask)
+    T.tr_tuning_set(reg.h, 4000, 8, cfg(7, 3, 8, 5, 4096))   # a second group
+    path = str(tmp_path / "tuning.txt")
+    T.tr_tuning_save(reg.h, path)
+    r0, m0 = run_single(reg, torch, p.src, p.dst, prm)
+    ref = snapshot(reg, r0, m0)
+    header = open(path).readline().split()
+    assert header[0] == "turboreg-tuning" and header[1] == "1"
+    fresh = T.Registrar(max_n=3000, max_batch=8, max_k1=600, max_k2=3)
+    try:
+        T.tr_tuning_load(fresh.h, path)
+        assert bytes(T.tr_tuning_get(fresh.h, c.n, 1)) == bytes(best)
+        assert bytes(T.tr_tuning_get(fresh.h, 4000, 8)) == bytes(cfg(7, 3, 8, 5, 4096))
+        r1, m1 = run_single(fresh, torch, p.src, p.dst, prm)
+        assert same(snapshot(fresh, r1, m1), ref)
+    finally:
+        fresh.close()
+    os.environ["TURBOREG_TUNING_CACHE"] = path
+    try:
+        env = T.Registrar(max_n=3000, max_batch=1, max_k1=600, max_k2=3)
+        assert bytes(T.tr_tuning_get(env.h, c.n, 1)) == bytes(best)
+        env.close()
+    finally:
+        del os.environ["TURBOREG_TUNING_CACHE"]
+    lines = open(path).read().splitlines()
+    extra = "9 2 3 3 4 3 1024"   # a group (2304 rows, B = 2) that a refused file must not set
+    bad = {"version": [lines[0].replace("turboreg-tuning 1", "turboreg-tuning 2")] + lines[1:] + [extra],
+           "arch": [" ".join(header[:2] + ["gfx000"] + header[3:])] + lines[1:] + [extra],
+           "cus": [" ".join(header[:3] + [str(int(header[3]) + 1)])] + lines[1:] + [extra],
+           "range": lines + [extra, "6 1 5 4 6 4 0"],
+           "short": lines + [extra, "6 1 5"]}
+    before = bytes(T.tr_tuning_get(reg.h, 2304, 2))
+    assert before != bytes(cfg(3, 3, 4, 3, 1024))
+    for name, content in bad.items():
+        q = str(tmp_path / f"bad_{name}.txt")
+        open(q, "w").write("\n".join(content) + "\n")
+        with pytest.raises(T.TurboRegError):
+            T.tr_tuning_load(reg.h, q)
+        assert bytes(T.tr_tuning_get(reg.h, 2304, 2)) == before, name
+    good = str(tmp_path / "good_extra.txt")
+    open(good, "w").write("\n".join(lines + [extra]) + "\n")
+    T.tr_tuning_load(reg.h, good)
+    assert bytes(T.tr_tuning_get(reg.h, 2304, 2)) == bytes(cfg(3, 3, 4, 3, 1024))
