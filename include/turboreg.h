@@ -199,8 +199,9 @@ tr_status tr_tuning_load(tr_handle *h, const char *path);
  * if offsets_dev is NULL and B == 1, else the batch as tr_register_batch) under
  * candidate configurations, one field at a time starting from the group's
  * current one (hyp_ppw, hyp_per_cu, sc2_super, compat_per_cu, sc2_sparse_cap), each candidate
- * timed by HIP events on `stream` over five runs after one warm-up, keeps a
- * candidate only if it is at least 1% faster, stores the result for the group
+ * timed by HIP events on `stream` as the fastest of three batches of eight runs after one
+ * warm-up, with the incumbent timed again beside it, keeps a candidate only if it is at
+ * least 2% faster, stores the result for the group
  * and writes it to *best (nullable) with its time per registration call in
  * *best_ms (nullable). Runs eagerly and synchronises the stream; out_dev and
  * masks_dev receive the results of the last run. Same argument errors as the

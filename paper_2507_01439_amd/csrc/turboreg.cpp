@@ -737,17 +737,25 @@ tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const in
         if (e0) hipEventDestroy(e0);
         return TR_ERR_HIP;
     }
-    constexpr int kRuns = 5;
-    // average milliseconds of one call under configuration c (one untimed warm-up)
+    constexpr int kRuns = 8, kBatches = 3;
+    // milliseconds of one call under configuration c: after one untimed warm-up, the fastest of
+    // three batches of eight back-to-back calls (the minimum is robust to interference)
     auto time_cfg = [&](const tr_tuning &c, float &ms) -> tr_status {
-        for (int r = 0; r <= kRuns; ++r) {
-            if (r == 1 && hipEventRecord(e0, s) != hipSuccess) return TR_ERR_HIP;
-            tr_status q = enqueue(h, w, offsets_dev, n_single, B, max_n, nullptr, 0, false, s, c);
-            if (q != TR_OK) return q;
+        tr_status q = enqueue(h, w, offsets_dev, n_single, B, max_n, nullptr, 0, false, s, c);
+        if (q != TR_OK) return q;
+        ms = 0.0f;
+        for (int bt = 0; bt < kBatches; ++bt) {
+            if (hipEventRecord(e0, s) != hipSuccess) return TR_ERR_HIP;
+            for (int r = 0; r < kRuns; ++r) {
+                q = enqueue(h, w, offsets_dev, n_single, B, max_n, nullptr, 0, false, s, c);
+                if (q != TR_OK) return q;
+            }
+            float t = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return TR_ERR_HIP;
+            if (hipEventElapsedTime(&t, e0, e1) != hipSuccess) return TR_ERR_HIP;
+            t /= kRuns;
+            if (bt == 0 || t < ms) ms = t;
         }
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return TR_ERR_HIP;
-        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return TR_ERR_HIP;
-        ms /= kRuns;
         return TR_OK;
     };
     tr_tuning cur = tuning_for(h, max_n, B);
@@ -771,9 +779,13 @@ tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const in
             if (fd.v[k] == start) continue;
             tr_tuning c = cur;
             c.*fd.f = fd.v[k];
-            float ms = 0.0f;
+            float ms = 0.0f, again = 0.0f;
             st = time_cfg(c, ms);
-            if (st == TR_OK && ms < 0.99f * cur_ms) {
+            // the incumbent is timed again beside each candidate (drift); a candidate must be at
+            // least 2% faster
+            if (st == TR_OK) st = time_cfg(cur, again);
+            if (st == TR_OK) cur_ms = std::min(cur_ms, again);
+            if (st == TR_OK && ms < 0.98f * cur_ms) {
                 cur = c;
                 cur_ms = ms;
             }
