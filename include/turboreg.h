@@ -129,8 +129,10 @@ tr_status tr_register_noalloc(const float *src, const float *dst, int32_t n, con
  * [offsets[b], offsets[b+1]) of src/dst; offsets_dev is B+1 int32 in device
  * memory, non-decreasing, every N_b <= max_n (host-side bound, <= the handle's).
  * A pair with N_b < 3 or N_b > max_n gets status TR_ERR_INVALID_ARG. out_dev is
- * B results; masks_dev (nullable) is offsets[B] uint8. The launch sequence is
- * captured once into a hipGraph per (pointers, B, max_n, params) and replayed. */
+ * B results; masks_dev (nullable) is offsets[B] uint8. On a stream other than the
+ * legacy default one, the launch sequence is captured once into a hipGraph per
+ * (pointers, stream, B, max_n, params) and replayed; a handle keeps the 8 most recently
+ * launched graphs, and a call that must evict one first waits for the whole device. */
 tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst,
                             const int32_t *offsets_dev, int32_t B, int32_t max_n,
                             const tr_params *p, tr_result *out_dev, uint8_t *masks_dev,

@@ -24,8 +24,10 @@ constexpr int kTickHyp0 = kCollectRegions;      // first clique-search group tic
 constexpr int kFusedPool = 512;   // learned pools up to this size are reordered inside the hypothesis kernel
 
 // Work-list stages whose per-pair item counts depend on N_b; each has a
-// prefix array of B+1 entries in Plan::pre.
+// prefix array of B+1 entries in Work::pre, over the pairs in cost order.
 enum Stage { kPrep = 0, kCompat, kSc2, kRowBlk, kScore, kNumPrefix };
+// Rows of Work::pre after the stage prefixes: the cost order (slot -> pair), its inverse.
+constexpr int kOrderRow = kNumPrefix, kSlotRow = kNumPrefix + 1, kPreRows = kNumPrefix + 2;
 
 struct PairDesc {
     int32_t n;        // matches in this pair (0 when the pair is invalid)
@@ -54,6 +56,7 @@ struct PairState {
 struct Plan {
     int32_t B;
     int32_t total[kNumPrefix];
+    int32_t sc2_split[9];   // SC2 items [sc2_split[x], sc2_split[x+1]) go to XCD x: equal modelled cost
 };
 
 // Device views passed to every kernel.
@@ -62,7 +65,9 @@ struct Work {
     const PairDesc *pairs;
     PairState *state;
     const Plan *plan;
-    const int32_t *pre;       // kNumPrefix x (max_batch + 1)
+    const int32_t *pre;       // kPreRows x (max_batch + 1): per stage, the first item of the pair in
+                              // each slot of the cost order (largest pairs first); then the order
+                              // (slot -> pair) and its inverse (pair -> slot)
     int32_t pre_stride;       // max_batch + 1
     int32_t n1;               // N of a single-pair call (its plan is computed in registers), 0 for a batch
     int32_t max_n;            // per-pair row stride of the per-row arenas
@@ -206,11 +211,21 @@ __host__ __device__ inline int64_t stage_items(int stage, int32_t n, int32_t H)
     }
 }
 
-// Work lists: all items of a stage, pair after pair. A single-pair call (n1 > 0)
+// Work lists: all items of a stage, pair after pair, in the plan's slot order: for batches of
+// 16 pairs or more, the pairs sorted by decreasing size (npad; pairs of one size in index order) and dealt to the eight XCDs, each
+// XCD's pairs in size order, so that eight SC2 ranges of equal cost hold like mixes of sizes and
+// a workgroup striding through a list takes costly items first. A single-pair call (n1 > 0)
 // derives everything from n1; a batch reads the device plan.
 __device__ __forceinline__ int stage_total(const Work &w, int stage)
 {
     return w.n1 ? (int)stage_items(stage, w.n1, w.H) : w.plan->total[stage];
+}
+
+// The pair in slot k of the cost order (kernels with one workgroup, or a fixed number, per
+// pair take their pairs in this order too).
+__device__ __forceinline__ int batch_pair(const Work &w, int k)
+{
+    return w.n1 ? k : w.pre[kOrderRow * w.pre_stride + k];
 }
 
 // The pair an item belongs to, and the item's index inside that pair.
@@ -221,21 +236,22 @@ __device__ __forceinline__ int stage_pair(const Work &w, int stage, int item, in
         return 0;
     }
     const int32_t *pre = w.pre + stage * w.pre_stride;
-    const int b = find_pair(pre, w.plan->B, item);
-    local = item - pre[b];
-    return b;
+    const int k = find_pair(pre, w.plan->B, item);
+    local = item - pre[k];
+    return w.pre[kOrderRow * w.pre_stride + k];
 }
 
 // First item of pair b in a stage's list, and its item count.
 __device__ __forceinline__ int stage_first(const Work &w, int stage, int b)
 {
-    return w.n1 ? 0 : w.pre[stage * w.pre_stride + b];
+    return w.n1 ? 0 : w.pre[stage * w.pre_stride + w.pre[kSlotRow * w.pre_stride + b]];
 }
 
 __device__ __forceinline__ int stage_count(const Work &w, int stage, int b)
 {
-    return w.n1 ? (int)stage_items(stage, w.n1, w.H)
-                : w.pre[stage * w.pre_stride + b + 1] - w.pre[stage * w.pre_stride + b];
+    if (w.n1) return (int)stage_items(stage, w.n1, w.H);
+    const int k = w.pre[kSlotRow * w.pre_stride + b];
+    return w.pre[stage * w.pre_stride + k + 1] - w.pre[stage * w.pre_stride + k];
 }
 
 __device__ __forceinline__ PairDesc pair_desc(const Work &w, int b)

@@ -94,49 +94,187 @@ __device__ void block_scan_multi(const int64_t (&v)[NV], int64_t (&excl)[NV], in
     __syncthreads();
 }
 
-// One workgroup: per-pair sizes, work-item counts and their prefix sums, arena
-// offsets, and zeroed per-pair state.
+constexpr int kCostKeys = 32767 / kSc2Tile + 2;   // npad / kSc2Tile of a valid pair (max_n <= 32767), 0 if invalid
+constexpr int kOrderMinB = 16;   // smaller batches keep their pairs in index order
+
+// Slot of the pair at position p of the size order (largest first) among B pairs: the order is
+// dealt to the eight XCDs in a snake (positions 0-7 to XCDs 0-7, 8-15 to XCDs 7-0, ...), and the
+// slots hold XCD 0's pairs, then XCD 1's, ..., each XCD's pairs in size order. Cut into eight
+// ranges of equal cost, the SC2 list then gives each XCD a like mix of sizes, costly items first.
+__device__ __forceinline__ int xcd_pairs(int x, int B)
+{
+    const int R = B >> 3, rem = B & 7;
+    return R + (rem && ((R & 1) ? x >= 8 - rem : x < rem));
+}
+
+__device__ __forceinline__ int xcd_first_slot(int x, int B)
+{
+    int first = 0;
+    for (int y = 0; y < x; ++y) first += xcd_pairs(y, B);
+    return first;
+}
+
+__device__ __forceinline__ int snake_slot(int p, int B)
+{
+    const int r = p >> 3, c = p & 7;
+    return xcd_first_slot((r & 1) ? 7 - c : c, B) + r;
+}
+
+// One workgroup: per-pair sizes, arena offsets (pair order) and zeroed per-pair state; the
+// order of the pairs (from 16 pairs on: by decreasing npad, pairs of one size in index order,
+// dealt to the XCDs; else index order);
+// the work-item counts of every stage and their prefix sums over that order; the XCD ranges of
+// the SC2 list, equal in modelled cost.
 __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n_single, int32_t B,
                                                int32_t max_n, int32_t pool, int32_t H,
                                                PairDesc *pairs, PairState *state, Plan *plan,
                                                int32_t *pre, int32_t pre_stride)
 {
-    constexpr int NV = kNumPrefix + 1;   // the work-list stages, then the arena bytes
+    constexpr int NV = kNumPrefix + 1;   // the work-list stages, then the SC2 cost
     __shared__ int64_t lds[17][NV];
-    int64_t carry[NV] = {};
+    __shared__ int64_t lds1[17][2];
+    __shared__ int32_t kfirst[kCostKeys];        // pairs per size key, then the key's next free position
+    __shared__ int32_t wfirst[16][kCostKeys];    // per wave of a chunk: pairs per key, then first position
+    __shared__ int32_t nl[1024], ol[1024];       // B <= 1024: n of each valid pair (0 if invalid); the order
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = blockDim.x >> 6;
+    int32_t *order = pre + kOrderRow * pre_stride, *slot_of = pre + kSlotRow * pre_stride;
+    auto size_of = [&](int b, int32_t &n, int32_t &pt) {   // n and first match of pair b; valid?
+        n = pt = 0;
+        if (b >= B) return false;
+        if (offsets) { pt = offsets[b]; n = offsets[b + 1] - pt; }
+        else n = n_single;
+        return n >= 3 && n <= max_n;
+    };
+    const bool small = B <= 1024;
+    auto valid_n = [&](int b) {   // n of pair b if it is valid, else 0 (passes 2 and 3)
+        if (b >= B) return 0;
+        if (small) return nl[b];
+        int32_t n, pt;
+        return size_of(b, n, pt) ? n : 0;
+    };
+    // modelled cost of one SC2 item in K columns of its main loop: npad columns, plus the
+    // epilogue (scan, histogram, stores), which takes about as long as 2048 columns
+    auto sc2_unit = [](int32_t npad) { return (int64_t)npad + 2048; };
+    for (int k = tid; k < kCostKeys; k += blockDim.x) kfirst[k] = 0;
+    __syncthreads();
+    // pass 1, pair order: descriptors, state, arena offsets, size-key counts, total SC2 cost
+    int64_t acarry = 0, sc2_cost = 0;
     for (int base = 0; base < B; base += blockDim.x) {
-        const int b = base + threadIdx.x;
-        int32_t n = 0, pt = 0;
-        bool ok = false;
-        if (b < B) {
-            if (offsets) { pt = offsets[b]; n = offsets[b + 1] - pt; }
-            else n = n_single;
-            ok = n >= 3 && n <= max_n;
-        }
+        const int b = base + tid;
+        int32_t n, pt;
+        const bool ok = size_of(b, n, pt);
         const int32_t npad = ok ? (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile : 0;
-        int64_t cnt[NV], excl[NV], tot[NV];
-        for (int s = 0; s < kNumPrefix; ++s) cnt[s] = ok ? stage_items(s, n, H) : 0;
-        cnt[kScore] = ok ? cnt[kScore] : (b < B);   // an invalid pair's one (empty) scoring item writes its record
-        cnt[kNumPrefix] = (int64_t)npad * npad;   // arena entries
-        block_scan_multi<NV>(cnt, excl, tot, lds);
+        int64_t v[2] = {(int64_t)npad * npad, ok ? stage_items(kSc2, n, H) * sc2_unit(npad) : 0}, excl[2], tot[2];
+        block_scan_multi<2>(v, excl, tot, lds1);
         if (b < B) {
-            for (int s = 0; s < kNumPrefix; ++s) pre[s * pre_stride + b] = (int32_t)(excl[s] + carry[s]);
-            PairDesc d = pair_desc_of(n, pt, excl[kNumPrefix] + carry[kNumPrefix], pool);
+            PairDesc d = pair_desc_of(n, pt, excl[0] + acarry, pool);
             if (!ok) d.n = d.npad = d.kpiv = 0;
             pairs[b] = d;
             PairState st = {};
             st.status = ok ? TR_OK : TR_ERR_INVALID_ARG;
             state[b] = st;
+            atomicAdd(&kfirst[npad / kSc2Tile], 1);
+            if (small) nl[b] = ok ? n : 0;
+        }
+        acarry += tot[0];
+        sc2_cost += tot[1];
+    }
+    __syncthreads();
+    if (B < kOrderMinB) {   // a few pairs: slots in pair order
+        for (int b = tid; b < B; b += blockDim.x) {
+            order[b] = slot_of[b] = b;
+            if (small) ol[b] = b;
+        }
+    } else {
+        {   // first position of each key, the largest key first
+            int64_t v[2] = {tid < kCostKeys ? kfirst[kCostKeys - 1 - tid] : 0, 0}, excl[2], tot[2];
+            block_scan_multi<2>(v, excl, tot, lds1);
+            if (tid < kCostKeys) kfirst[kCostKeys - 1 - tid] = (int32_t)excl[0];
+            __syncthreads();
+        }
+        // pass 2, pair order: positions (pairs of one key in index order: rank in the wave by
+        // ballots, then the waves of the chunk in order), and slots
+        for (int base = 0; base < B; base += blockDim.x) {
+            const int b = base + tid;
+            const int key = (valid_n(b) + kSc2Tile - 1) / kSc2Tile;
+            const int nwa = min(nw, (B - base + 63) >> 6);   // waves of the chunk that hold pairs
+            for (int k = tid; k < nwa * kCostKeys; k += blockDim.x) (&wfirst[0][0])[k] = 0;
+            __syncthreads();
+            bool pending = b < B;
+            int rank = 0;
+            uint64_t todo = __ballot(pending);
+            while (todo) {
+                const int lk = __builtin_amdgcn_readlane(key, __builtin_ctzll(todo));
+                const bool mine = pending && key == lk;
+                const uint64_t m = __ballot(mine);
+                if (mine) {
+                    rank = __builtin_popcountll(m & ((1ull << lane) - 1));
+                    pending = false;
+                }
+                if (lane == 0) wfirst[wid][lk] = __builtin_popcountll(m);
+                todo &= ~m;
+            }
+            __syncthreads();
+            for (int k = tid; k < kCostKeys; k += blockDim.x) {
+                int32_t acc = kfirst[k];
+                for (int v = 0; v < nwa; ++v) {
+                    const int32_t c = wfirst[v][k];
+                    wfirst[v][k] = acc;
+                    acc += c;
+                }
+                kfirst[k] = acc;
+            }
+            __syncthreads();
+            if (b < B) {
+                const int slot = snake_slot(wfirst[wid][key] + rank, B);
+                order[slot] = b;
+                slot_of[b] = slot;
+                if (small) ol[slot] = b;
+            }
+            __syncthreads();   // wfirst is cleared next chunk
+        }
+    }
+    __syncthreads();   // order[] is read by other threads below
+    // pass 3, slot order: stage prefixes; SC2 range boundaries at x / 8 of the cost
+    if (tid == 0) {
+        plan->B = B;
+        plan->sc2_split[0] = 0;
+        for (int x = 1; x < 8; ++x)
+            if (sc2_cost * x / 8 == 0) plan->sc2_split[x] = 0;
+    }
+    int64_t carry[NV] = {};
+    for (int base = 0; base < B; base += blockDim.x) {
+        const int slot = base + tid;
+        const int b = slot >= B ? B : small ? ol[slot] : order[slot];
+        const int32_t n = valid_n(b);
+        const bool ok = n > 0;
+        int64_t cnt[NV], excl[NV], tot[NV];
+        for (int s = 0; s < kNumPrefix; ++s) cnt[s] = ok ? stage_items(s, n, H) : 0;
+        cnt[kScore] = ok ? cnt[kScore] : (b < B);   // an invalid pair's one (empty) scoring item writes its record
+        const int32_t npad = ok ? (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile : 0;
+        cnt[kNumPrefix] = ok ? cnt[kSc2] * sc2_unit(npad) : 0;
+        block_scan_multi<NV>(cnt, excl, tot, lds);
+        if (slot < B) {
+            for (int s = 0; s < kNumPrefix; ++s) pre[s * pre_stride + slot] = (int32_t)(excl[s] + carry[s]);
+            // a target in (c0, c1] falls in this pair's items: the first item whose cost prefix reaches it
+            const int64_t c0 = excl[kNumPrefix] + carry[kNumPrefix], c1 = c0 + cnt[kNumPrefix];
+            for (int x = 1; x < 8; ++x) {
+                const int64_t tgt = sc2_cost * x / 8;
+                if (tgt > c0 && tgt <= c1) {
+                    const int64_t u = sc2_unit(npad);
+                    plan->sc2_split[x] = (int32_t)(excl[kSc2] + carry[kSc2] + (tgt - c0 + u - 1) / u);
+                }
+            }
         }
 #pragma unroll
         for (int s = 0; s < NV; ++s) carry[s] += tot[s];
     }
-    if (threadIdx.x == 0) {
-        plan->B = B;
+    if (tid == 0) {
         for (int s = 0; s < kNumPrefix; ++s) {
             pre[s * pre_stride + B] = (int32_t)carry[s];
             plan->total[s] = (int32_t)carry[s];
         }
+        plan->sc2_split[8] = (int32_t)carry[kSc2];
     }
 }
 
@@ -496,14 +634,17 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
     const int total = stage_total(w, kSc2);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv >> 1, wn = wv & 1;
     const int xcd = blockIdx.x & 7, nx = (gridDim.x - xcd + 7) >> 3, lb = blockIdx.x >> 3;
+    // XCD x takes a contiguous range of the list (neighbouring tiles share rows of C in its L2):
+    // equal counts for one pair, equal shares of the modelled cost for a batch
     const int chunk = (total + 7) >> 3;
-    const int end = min(total, (xcd + 1) * chunk);
+    const int start = w.n1 ? xcd * chunk : w.plan->sc2_split[xcd];
+    const int end = w.n1 ? min(total, (xcd + 1) * chunk) : w.plan->sc2_split[xcd + 1];
     // fragment read offsets inside a stage: row (lane & 31) of a 32-row block, chunk (ks*2 + lane/32)
     const int frow = lane & 31, fsw = (frow >> 2) & 3;
     const int foff0 = frow * kBK + 16 * ((lane >> 5) ^ fsw), foff1 = frow * kBK + 16 * ((2 + (lane >> 5)) ^ fsw);
     for (int k = tid; k < kHistLdsBins; k += 256) hist[k] = 0;
     __syncthreads();
-    for (int item = xcd * chunk + lb; item < end; item += nx) {
+    for (int item = start + lb; item < end; item += nx) {
         int local;
         const int b = stage_pair(w, kSc2, item, local);
         const PairDesc d = pair_desc(w, b);

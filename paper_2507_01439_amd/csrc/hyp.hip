@@ -596,7 +596,7 @@ __global__ void __launch_bounds__(64 * NW) k_hyp(Work w, int B, int ppw)
     const int ipp = (w.k1 + ppw - 1) / ppw, total = B * ipp;
     const float th2 = w.theta * w.theta;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        const int b = item / ipp, g = item - b * ipp;
+        const int slot = item / ipp, b = batch_pair(w, slot), g = item - slot * ipp;
         const PairDesc d = pair_desc(w, b);
         const int nloc = ppw * w.k2;   // local hypothesis hl = (pivot lp) * K2 + slot
         // profiled calls: phase stamps of thread 0 (clique search of wave 0's pivots, fits up to

@@ -255,7 +255,7 @@ __global__ void __launch_bounds__(256) k_cand_rows(Work w, int B, int R, const u
     const float inv_q = 1.0f / q, guard0 = __builtin_fmaf(q, 0x1p-17f, 2e-6f);
     const int cpp = (2 * w.pool + R - 1) / R, total = B * cpp;
     for (int c = blockIdx.x; c < total; c += gridDim.x) {
-        const int b = c / cpp, e0 = (c - b * cpp) * R;
+        const int slot = c / cpp, b = batch_pair(w, slot), e0 = (c - slot * cpp) * R;
         const PairDesc d = pair_desc(w, b);
         if (e0 < 2 * d.kpiv) {   // the same for the whole workgroup
             // Two batches of kU points per thread are in flight before the rows are claimed
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(256) k_reorder(Work w, int blocks_per_pair)
 {
     extern __shared__ uint64_t keys[];
     __shared__ int32_t part[4][64];
-    const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
+    const int slot = blockIdx.x / blocks_per_pair, b = batch_pair(w, slot), g = blockIdx.x - slot * blocks_per_pair;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv;

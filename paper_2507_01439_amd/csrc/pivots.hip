@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(1024) k_thresh(Work w)
     extern __shared__ int32_t hs[];
     __shared__ int32_t res[3], wtot[16];
     __shared__ int32_t tally[16][3];
-    const int b = blockIdx.x;
+    const int b = batch_pair(w, blockIdx.x);
     const PairDesc d = pair_desc(w, b);
     const int64_t K = d.kpiv;
     // this call's counters of the pair (collection regions, clique-search tickets) start at zero;
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort(Work w, int blocks_per_pa
     __shared__ int32_t part[kSortWaves][64];
     __shared__ int64_t lds[17];
     __shared__ int32_t nrel, rel_blk[64], rel_pre[64];
-    const int b = blockIdx.x / blocks_per_pair, g = blockIdx.x - b * blocks_per_pair;
+    const int slot = blockIdx.x / blocks_per_pair, b = batch_pair(w, slot), g = blockIdx.x - slot * blocks_per_pair;
     const PairDesc d = pair_desc(w, b);
     const int K = d.kpiv, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     // the collection counters are read together with the state (they are zeroed for every pair)

@@ -77,8 +77,15 @@ struct tr_handle {
     int64_t ring_next = 0;
     double stage_sum[TR_NUM_STAGES] = {};
     int64_t stage_calls[TR_NUM_STAGES] = {};
-    // captured batches
-    std::map<GraphKey, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // captured batches, at most kMaxGraphs, the least recently launched evicted first
+    struct Captured {
+        hipGraph_t g;
+        hipGraphExec_t ge;
+        uint64_t last_use;
+    };
+    static constexpr size_t kMaxGraphs = 8;
+    std::map<GraphKey, Captured> graphs;
+    uint64_t graph_clock = 0;
     // launch configurations by (256-row tiles of the largest pair, batch size)
     std::map<std::pair<int32_t, int32_t>, tr_tuning> tuning;
     std::vector<void *> allocs;
@@ -100,8 +107,8 @@ hipError_t alloc(tr_handle *h, T **p, size_t count)
 void release(tr_handle *h)
 {
     for (auto &g : h->graphs) {
-        hipGraphExecDestroy(g.second.second);
-        hipGraphDestroy(g.second.first);
+        hipGraphExecDestroy(g.second.ge);
+        hipGraphDestroy(g.second.g);
     }
     h->graphs.clear();
     for (auto &e : h->ring)
@@ -141,7 +148,7 @@ void workspace_layout(tr_handle *h, Get &&get)
     get(h->pairs, B);
     get(h->state, B);
     get(h->plan, 1);
-    get(h->pre, (size_t)kNumPrefix * h->pre_stride);
+    get(h->pre, (size_t)kPreRows * h->pre_stride);
     get(h->C, B * nn / 2);   // packed E2M1, two entries per byte
     get(h->Cbits, B * nn / 8);   // the same matrix as bits
     get(h->G, B * nn);
@@ -320,9 +327,10 @@ tr_status enqueue(tr_handle *h, const Work &w_in, const int32_t *offsets, int32_
     chk(launch_compat(w, grid_cap(h, (int64_t)B * nb64 * (nb64 + 1) / 2, cfg.compat_per_cu), s));
     mark(TR_STAGE_SC2);
     {
-        // one workgroup per CU; the kernel splits its items into 8 equal ranges, one per XCD
-        // (workgroup g runs on XCD g mod 8), so the grid is a multiple of 8 with as many
-        // workgroups per XCD as its range holds items, up to the XCD's CUs
+        // one workgroup per CU; the kernel splits its items into 8 ranges, one per XCD
+        // (workgroup g runs on XCD g mod 8), of equal counts for one pair and of equal modelled
+        // cost for a batch, so the grid is a multiple of 8 with as many workgroups per XCD as an
+        // even range would hold items, up to the XCD's CUs
         const int64_t items = (int64_t)B * nbs * (nbs + 1) / 2;
         const int64_t per_xcd = std::min<int64_t>((items + 7) / 8, std::max(1, h->num_cus / 8));
         chk(launch_sc2(w, (int)(8 * per_xcd), s));
@@ -614,6 +622,17 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
     key.cfg = cfg;
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
+        if (h->graphs.size() >= tr_handle::kMaxGraphs) {
+            // a launch of the evicted graph may still run (on any stream): wait for the device
+            // before destroying it; only callers that cycle through more buffer sets pay this
+            auto lru = h->graphs.begin();
+            for (auto jt = h->graphs.begin(); jt != h->graphs.end(); ++jt)
+                if (jt->second.last_use < lru->second.last_use) lru = jt;
+            if (hipDeviceSynchronize() != hipSuccess) return TR_ERR_HIP;
+            hipGraphExecDestroy(lru->second.ge);
+            hipGraphDestroy(lru->second.g);
+            h->graphs.erase(lru);
+        }
         hipGraph_t g = nullptr;
         hipGraphExec_t ge = nullptr;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return TR_ERR_HIP;
@@ -627,9 +646,10 @@ tr_status tr_register_batch(tr_handle *h, const float *src, const float *dst, co
             hipGraphDestroy(g);
             return TR_ERR_HIP;
         }
-        it = h->graphs.emplace(key, std::make_pair(g, ge)).first;
+        it = h->graphs.emplace(key, tr_handle::Captured{g, ge, 0}).first;
     }
-    if (hipGraphLaunch(it->second.second, s) != hipSuccess) return TR_ERR_HIP;
+    it->second.last_use = ++h->graph_clock;
+    if (hipGraphLaunch(it->second.ge, s) != hipSuccess) return TR_ERR_HIP;
     remember(h, w, B, s);
     return TR_OK;
 }

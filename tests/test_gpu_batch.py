@@ -53,6 +53,29 @@ def test_batch_uneven_matches_oracle(reg):
         check_taps(reg, X, Y, prm, r, masks[offs[b]:offs[b + 1]], pair=b, label=f"batch pair {b} n={n}")
 
 
+def test_batch_in_size_order_matches_oracle():
+    # 21 pairs (a batch large enough for the size-ordered work lists: pairs sorted by tile count
+    # and dealt to the XCDs), with sizes across several tile counts, equal sizes and invalid pairs
+    ns = [700, 2, 256, 257, 640, 3, 512, 700, 100, 0, 513, 300, 699, 64, 255, 600, 5, 450, 700, 1, 333]
+    r = T.Registrar(max_n=700, max_batch=len(ns), max_k1=200, max_k2=2)
+    try:
+        pairs, src, dst, offs = make_batch([max(n, 0) for n in ns], 5)
+        prm = T.make_params(0.1, 0.1, k1=150, k2=2)
+        say(f"batch in size order: {len(ns)} pairs")
+        out, masks = r.register_batch(to_dev(torch, src), to_dev(torch, dst), to_dev(torch, offs), prm, max_n=700)
+        torch.cuda.synchronize()
+        res = T.parse_results(out, len(ns))
+        masks = masks.cpu().numpy()
+        for b, n in enumerate(ns):
+            if n < 3:
+                assert res[b].status == T.TR_ERR_INVALID_ARG and res[b].best_hyp == -1, b
+                continue
+            X, Y = src[offs[b]:offs[b + 1]], dst[offs[b]:offs[b + 1]]
+            check_taps(r, X, Y, prm, res[b], masks[offs[b]:offs[b + 1]], pair=b, label=f"pair {b} n={n}")
+    finally:
+        r.close()
+
+
 def test_batch_equals_single(reg):
     ns = [400, 900, 128]
     pairs, src, dst, offs = make_batch(ns, 2)
@@ -96,6 +119,35 @@ def test_graph_replay_matches_eager(reg):
         for b in range(len(ns)):
             X, Y = s2[offs[b]:offs[b + 1]], d2[offs[b]:offs[b + 1]]
             check_taps(reg, X, Y, prm, res[b], graph_masks[offs[b]:offs[b + 1]], pair=b, label=f"replay {rep} pair {b}")
+
+
+def test_graph_cache_eviction(reg):
+    # twelve output buffer sets on one side stream, more than the eight graphs a handle keeps,
+    # then the first sets again (evicted by now, so captured anew): every launch equals the
+    # eager result, and the graphs launched before an eviction finished with their own bits
+    ns = [500, 260, 1100]
+    prm = T.make_params(0.1, 0.1, k1=200, k2=2)
+    side = torch.cuda.Stream()            # default priority
+    _, src, dst, offs = make_batch(ns, 4)
+    d_src, d_dst, d_offs = to_dev(torch, src), to_dev(torch, dst), to_dev(torch, offs)
+    e_out, e_masks = reg.register_batch(d_src, d_dst, d_offs, prm, max_n=1500)
+    torch.cuda.synchronize()
+    want, want_masks = e_out.cpu().numpy(), e_masks.cpu().numpy()
+    sets = [(torch.full((80 * len(ns),), 0xAB, dtype=torch.uint8, device="cuda"),
+             torch.full((int(offs[-1]),), 0xAB, dtype=torch.uint8, device="cuda")) for _ in range(12)]
+    torch.cuda.synchronize()
+    order = list(range(12)) + [0, 1, 2]
+    say(f"graph cache: {len(order)} launches over {len(sets)} buffer sets")
+    with torch.cuda.stream(side):
+        for k in order:
+            out, masks = sets[k]
+            out.fill_(0xAB)
+            masks.fill_(0xAB)
+            T.tr_register_batch(reg.h, d_src, d_dst, d_offs, len(ns), 1500, prm, out, masks)
+    side.synchronize()
+    for k, (out, masks) in enumerate(sets):
+        assert np.array_equal(out.cpu().numpy(), want), f"buffer set {k}"
+        assert np.array_equal(masks.cpu().numpy(), want_masks), f"buffer set {k}"
 
 
 def test_batch_success_on_indoor_pairs(reg):
