@@ -10,6 +10,15 @@ namespace tr {
 constexpr int kSc2Tile = 256;     // output tile edge of the FP4 MFMA SC2 kernel; npad is a multiple
 constexpr int kHistGroups = 8;    // SC2 tiles add their weight histograms into this many copies per pair
 constexpr int kCompatTile = 64;   // tile edge of the compatibility kernel
+// Row pitch of C in bytes: npad / 2 packed entries, plus 64 bytes where npad / 2 is a multiple
+// of 512, so that the rows an SC2 stage reads (one 64-byte chunk of each of 256 rows) are not all
+// at one offset modulo 512 bytes. At N = 5000 (npad / 2 = 2560) the padding made the SC2 kernel
+// 1.2-1.9 us faster; padding every pitch made the uneven 256-pair batch 1 % slower.
+constexpr int kCRowPad = 64;
+__host__ __device__ inline int64_t c_pitch(int32_t npad)
+{
+    return npad / 2 + ((npad & 1023) == 0 ? kCRowPad : 0);
+}
 constexpr int kRowsPerItem = 4;   // rows per work item of the pivot scans (one per wave)
 constexpr int kPrepRows = 256;    // rows per work item of the prep / feature kernels
 constexpr int kRankSortMax = 4096; // candidate lists up to this size are ordered by a rank sort
@@ -34,8 +43,9 @@ struct PairDesc {
     int32_t npad;     // n rounded up to kSc2Tile
     int32_t pt_off;   // first match of this pair in src/dst
     int32_t kpiv;     // pivots to select: min(k1 or pool, n(n-1)/2)
-    int64_t c_off;    // entry offset of this pair's C in the C arena (npad x npad E2M1, bytes = c_off / 2)
+    int64_t c_off;    // entry offset of this pair in the npad x npad arenas (the bit rows of C: c_off / 8 bytes)
     int64_t g_off;    // element offset of this pair's G in the G arena (npad x npad uint16)
+    int64_t cb_off;   // byte offset of this pair's C (E2M1 nibbles, npad rows of c_pitch(npad) bytes)
 };
 
 // Per-pair scalars written by the kernels.
@@ -185,7 +195,8 @@ __device__ __forceinline__ int find_pair(const int32_t *pre, int B, int item)
 // Per-pair sizes of a valid pair (3 <= n <= max_n): the descriptor and the
 // work items of every stage. The device planner and single-pair calls (which
 // compute their plan in registers) use the same formulas.
-__host__ __device__ inline PairDesc pair_desc_of(int32_t n, int32_t pt_off, int64_t arena_off, int32_t pool)
+__host__ __device__ inline PairDesc pair_desc_of(int32_t n, int32_t pt_off, int64_t arena_off, int64_t c_bytes_off,
+                                                 int32_t pool)
 {
     PairDesc d;
     d.n = n;
@@ -195,6 +206,7 @@ __host__ __device__ inline PairDesc pair_desc_of(int32_t n, int32_t pt_off, int6
     d.kpiv = (int32_t)(pairs_all < pool ? pairs_all : pool);
     d.c_off = arena_off;
     d.g_off = arena_off;
+    d.cb_off = c_bytes_off;
     return d;
 }
 
@@ -256,7 +268,7 @@ __device__ __forceinline__ int stage_count(const Work &w, int stage, int b)
 
 __device__ __forceinline__ PairDesc pair_desc(const Work &w, int b)
 {
-    return w.n1 ? pair_desc_of(w.n1, 0, 0, w.pool) : w.pairs[b];
+    return w.n1 ? pair_desc_of(w.n1, 0, 0, 0, w.pool) : w.pairs[b];
 }
 
 // Ascending bitonic sort of P keys in LDS by one workgroup (P a power of two,

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
 {
     constexpr int NV = kNumPrefix + 1;   // the work-list stages, then the SC2 cost
     __shared__ int64_t lds[17][NV];
-    __shared__ int64_t lds1[17][2];
+    __shared__ int64_t lds1[17][3];
     __shared__ int32_t kfirst[kCostKeys];        // pairs per size key, then the key's next free position
     __shared__ int32_t wfirst[16][kCostKeys];    // per wave of a chunk: pairs per key, then first position
     __shared__ int32_t nl[1024], ol[1024];       // B <= 1024: n of each valid pair (0 if invalid); the order
@@ -158,16 +158,17 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
     for (int k = tid; k < kCostKeys; k += blockDim.x) kfirst[k] = 0;
     __syncthreads();
     // pass 1, pair order: descriptors, state, arena offsets, size-key counts, total SC2 cost
-    int64_t acarry = 0, sc2_cost = 0;
+    int64_t acarry = 0, ccarry = 0, sc2_cost = 0;
     for (int base = 0; base < B; base += blockDim.x) {
         const int b = base + tid;
         int32_t n, pt;
         const bool ok = size_of(b, n, pt);
         const int32_t npad = ok ? (n + kSc2Tile - 1) / kSc2Tile * kSc2Tile : 0;
-        int64_t v[2] = {(int64_t)npad * npad, ok ? stage_items(kSc2, n, H) * sc2_unit(npad) : 0}, excl[2], tot[2];
-        block_scan_multi<2>(v, excl, tot, lds1);
+        int64_t v[3] = {(int64_t)npad * npad, ok ? stage_items(kSc2, n, H) * sc2_unit(npad) : 0,
+                        ok ? npad * c_pitch(npad) : 0}, excl[3], tot[3];
+        block_scan_multi<3>(v, excl, tot, lds1);
         if (b < B) {
-            PairDesc d = pair_desc_of(n, pt, excl[0] + acarry, pool);
+            PairDesc d = pair_desc_of(n, pt, excl[0] + acarry, excl[2] + ccarry, pool);
             if (!ok) d.n = d.npad = d.kpiv = 0;
             pairs[b] = d;
             PairState st = {};
@@ -178,6 +179,7 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
         }
         acarry += tot[0];
         sc2_cost += tot[1];
+        ccarry += tot[2];
     }
     __syncthreads();
     if (B < kOrderMinB) {   // a few pairs: slots in pair order
@@ -187,8 +189,8 @@ __global__ void __launch_bounds__(1024) k_plan(const int32_t *offsets, int32_t n
         }
     } else {
         {   // first position of each key, the largest key first
-            int64_t v[2] = {tid < kCostKeys ? kfirst[kCostKeys - 1 - tid] : 0, 0}, excl[2], tot[2];
-            block_scan_multi<2>(v, excl, tot, lds1);
+            int64_t v[3] = {tid < kCostKeys ? kfirst[kCostKeys - 1 - tid] : 0, 0, 0}, excl[3], tot[3];
+            block_scan_multi<3>(v, excl, tot, lds1);
             if (tid < kCostKeys) kfirst[kCostKeys - 1 - tid] = (int32_t)excl[0];
             __syncthreads();
         }
@@ -502,8 +504,8 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
         nedge = wave_sum(nedge);
         if (lane == 0) { red[wv][0] = nbnd; red[wv][1] = nedge; red[wv][2] = any_bad; }
         __syncthreads();
-        uint8_t *Cb = w.C + d.c_off / 2;   // packed rows of npad / 2 bytes
-        const int64_t rs = d.npad / 2;
+        uint8_t *Cb = w.C + d.cb_off;
+        const int64_t rs = c_pitch(d.npad);
         const int r = tid >> 2, c8 = (tid & 3) * 8;
         *reinterpret_cast<uint2 *>(Cb + ((int64_t)bi * kCompatTile + r) * rs + bj * (kCompatTile / 2) + c8) =
             *reinterpret_cast<const uint2 *>(&tile[0][r * kNibStride + c8]);
@@ -650,9 +652,9 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         const PairDesc d = pair_desc(w, b);
         int bi, bj;
         super_decode(local, d.npad / kSc2Tile, w.sc2_super, bi, bj);
-        const uint8_t *Cb = w.C + d.c_off / 2;
-        const int64_t rs = d.npad / 2;       // packed row bytes
-        const int nk = (int)(rs / kBK);
+        const uint8_t *Cb = w.C + d.cb_off;
+        const int64_t rs = c_pitch(d.npad);          // row pitch
+        const int nk = (int)(d.npad / 2 / kBK);      // stages over the packed row
         // ---- the tile's edges: thread t holds row t of the I block over the tile's 256 columns
         const uint8_t *Cbit = w.Cbits + d.c_off / 8;
         const int64_t kbs = (int64_t)d.npad * 16;   // bytes of one 128-column block over all rows

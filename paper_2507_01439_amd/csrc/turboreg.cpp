@@ -149,7 +149,7 @@ void workspace_layout(tr_handle *h, Get &&get)
     get(h->state, B);
     get(h->plan, 1);
     get(h->pre, (size_t)kPreRows * h->pre_stride);
-    get(h->C, B * nn / 2);   // packed E2M1, two entries per byte
+    get(h->C, B * (nn / 2 + (size_t)h->npad_max * kCRowPad));   // packed E2M1, two entries per byte, padded rows
     get(h->Cbits, B * nn / 8);   // the same matrix as bits
     get(h->G, B * nn);
     get(h->ghist, B * kHistGroups * (size_t)((max_n + 7) & ~(size_t)7));
@@ -851,7 +851,7 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
     if (hipStreamSynchronize(h->last_stream) != hipSuccess) return TR_ERR_HIP;
     const Work &w = h->last;
     PairDesc d;
-    if (w.n1) d = pair_desc_of(w.n1, 0, 0, w.pool);   // single-pair calls keep no device descriptor
+    if (w.n1) d = pair_desc_of(w.n1, 0, 0, 0, w.pool);   // single-pair calls keep no device descriptor
     else if (hipMemcpy(&d, h->pairs + pair, sizeof(d), hipMemcpyDeviceToHost) != hipSuccess) return TR_ERR_HIP;
     const size_t n = d.n;
     size_t need = 0;
@@ -865,7 +865,7 @@ tr_status tr_debug_copy(tr_handle *h, int32_t tap, int32_t pair, void *host_dst,
         if (bytes < need) return TR_ERR_INVALID_ARG;
         const size_t rb = (n + 1) / 2;
         std::vector<uint8_t> packed(rb * n);
-        if (n && hipMemcpy2D(packed.data(), rb, h->C + d.c_off / 2, (size_t)d.npad / 2, rb, n,
+        if (n && hipMemcpy2D(packed.data(), rb, h->C + d.cb_off, (size_t)c_pitch(d.npad), rb, n,
                              hipMemcpyDeviceToHost) != hipSuccess)
             return TR_ERR_HIP;
         uint8_t *o = static_cast<uint8_t *>(host_dst);
