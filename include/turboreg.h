@@ -163,7 +163,7 @@ tr_status tr_score_poses(tr_handle *h, const float *src, const float *dst, int32
  * Calls are grouped by shape: the number of 256-row tiles of their largest
  * pair, round_up(max_n, 256) / 256, and the batch size B (1 for tr_register).
  * Each group has a launch configuration; a group never tuned or set uses the
- * defaults (5, 4, 4 for one pair or 16 for a batch, 4, 0). No configuration
+ * defaults (5, 8, 4 for one pair or 16 for a batch, 4, 0). No configuration
  * changes any result: C, weights, pivots, cliques, poses, inlier numbers and
  * the selection are the same under every valid configuration. */
 typedef struct {

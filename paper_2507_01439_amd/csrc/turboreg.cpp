@@ -188,7 +188,7 @@ tr_tuning tuning_for(const tr_handle *h, int32_t max_n, int32_t B)
     if (it != h->tuning.end()) return it->second;
     tr_tuning t;
     t.sc2_super = 5;
-    t.compat_per_cu = 4;
+    t.compat_per_cu = 8;   // twice the workgroups a CU holds: late ones fill the slots that free first
     t.hyp_ppw = B == 1 ? 4 : 16;   // batches: more pivots per workgroup, fewer passes over each pair's matches
     t.hyp_per_cu = 4;
     t.sc2_sparse_cap = 0;
@@ -781,7 +781,7 @@ tr_status tr_autotune(tr_handle *h, const float *src, const float *dst, const in
     tr_tuning cur = tuning_for(h, max_n, B);
     float cur_ms = 0.0f;
     st = time_cfg(cur, cur_ms);
-    static const int kPpw[] = {4, 8, 16}, kPerCu[] = {2, 4, 8}, kSuper[] = {3, 4, 5, 6, 8}, kCompat[] = {2, 4, 8},
+    static const int kPpw[] = {4, 8, 16}, kPerCu[] = {2, 4, 8}, kSuper[] = {3, 4, 5, 6, 8}, kCompat[] = {4, 8, 16},
                      kSparse[] = {0, 1024, 2048, 4096, TR_SC2_SPARSE_CAP_MAX};
     struct Field {
         int32_t tr_tuning::*f;

@@ -41,7 +41,7 @@ def cfg(sup, compat, ppw, per_cu, sparse=0):
 
 def test_defaults_and_argument_errors(reg):
     d1 = T.tr_tuning_get(reg.h, 5000, 1)
-    assert (d1.sc2_super, d1.compat_per_cu, d1.hyp_ppw, d1.hyp_per_cu, d1.sc2_sparse_cap) == (5, 4, 4, 4, 0)
+    assert (d1.sc2_super, d1.compat_per_cu, d1.hyp_ppw, d1.hyp_per_cu, d1.sc2_sparse_cap) == (5, 8, 4, 4, 0)
     d8 = T.tr_tuning_get(reg.h, 1500, 8)
     assert d8.hyp_ppw == 16
     for bad in (cfg(0, 4, 4, 4), cfg(17, 4, 4, 4), cfg(5, 0, 4, 4), cfg(5, 4, 6, 4), cfg(5, 4, 20, 4),
