@@ -564,17 +564,21 @@ constexpr float kAccBias = 8388608.0f;         // 2^23: a count v < 2^16 is then
 // Bit-count path (tiles with few edges): Eq. 2 is needed only where C_ij = 1, so a tile holding at
 // most kSddmmCap edges counts popcount(row_i AND row_j) for each of its edges instead of forming
 // the dense product (the threshold is a launch parameter up to kSddmmCap; 0 turns the path and the
-// compatibility kernel's bit rows off). Rows arrive in chunks of kChunkKb 128-column blocks (bits); LDS layout:
-// two chunk buffers (I rows then J rows, [block][row][16 bytes] each), the edge list, the counts.
+// compatibility kernel's bit rows off). Rows arrive in chunks of kChunkKb 128-column blocks (bits),
+// kChunkBufs - 1 chunks in flight; each thread keeps its edges and their counts in registers.
+// LDS layout: the chunk buffers (I rows then J rows, [block][row][16 bytes] each); the edge list
+// lies in the last buffer, which receives no chunk before every thread has its edges.
 constexpr int kSddmmCap = 8192;                       // 32 edges per thread
+constexpr int kEdgesPerThread = kSddmmCap / 256;
 static_assert(kSddmmCap == TR_SC2_SPARSE_CAP_MAX, "the launch parameter's range is the path's capacity");
 constexpr int kChunkKb = 4;                           // 512 columns of C per chunk
 constexpr int kChunkSide = kChunkKb * kSc2Tile * 16;  // 16 KiB: one side's 256 rows of a chunk
 constexpr int kChunkBytes = 2 * kChunkSide;
-constexpr int kEdgeOff = 2 * kChunkBytes;             // edge list: uint16 (i_local << 8 | j_local)
-constexpr int kCntOff = kEdgeOff + 2 * kSddmmCap;     // counts: int32 per edge
-constexpr int kScanOff = kCntOff + 4 * kSddmmCap;     // four wave totals of the edge-count scan
-static_assert(kScanOff + 64 <= kRingBytes, "the bit-count path stays below the histogram");
+constexpr int kChunkBufs = 4;
+constexpr int kEdgeOff = (kChunkBufs - 1) * kChunkBytes;   // edge list: uint16 (i_local << 8 | j_local)
+constexpr int kScanOff = kEdgeOff + 2 * kSddmmCap;    // four wave totals of the edge-count scan
+static_assert(kChunkBufs * kChunkBytes <= kRingBytes && kScanOff + 64 <= kRingBytes,
+              "the bit-count path stays below the histogram");
 
 // Wait until at most N vector-memory loads of this wave are outstanding, then
 // meet the other waves. The memory clobber keeps LDS reads of the new stage
@@ -694,7 +698,6 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
         }
         if (sparse) {
             uint16_t *edgeL = reinterpret_cast<uint16_t *>(smem + kEdgeOff);
-            int32_t *cntL = reinterpret_cast<int32_t *>(smem + kCntOff);
             {
                 int pos = eprefix;
 #pragma unroll
@@ -704,77 +707,96 @@ __global__ void __launch_bounds__(256, 1) k_sc2(Work w)
                         const int c = __builtin_ctz(x);
                         x &= x - 1;
                         edgeL[pos] = (uint16_t)((tid << 8) | (32 * k + c));
-                        cntL[pos] = 0;
                         ++pos;
                     }
                 }
             }
             __syncthreads();   // the edge list is complete
-            // thread t counts edges [e0, e1): about etotal / 256 consecutive edges (few rows each)
-            const int q = (etotal + 255) >> 8, e0 = min(etotal, tid * q), e1 = min(etotal, e0 + q);
+            // thread t counts edges [e0, e1): about etotal / 256 consecutive edges (few rows each),
+            // held in registers with their counts
+            const int q = (etotal + 255) >> 8, e0 = min(etotal, tid * q), e1 = min(etotal, e0 + q), ne = e1 - e0;
+            uint32_t myv[kEdgesPerThread];
+            int myc[kEdgesPerThread];
+#pragma unroll
+            for (int k = 0; k < kEdgesPerThread; ++k) {
+                myv[k] = k < ne ? edgeL[e0 + k] : 0u;
+                myc[k] = 0;
+            }
+            __syncthreads();   // the edge list's buffer may now receive a chunk
             const int nkb = d.npad / 128, nch = (nkb + kChunkKb - 1) / kChunkKb;
-            // chunk c: blocks 4c.. of the I rows (and J rows off the diagonal) by direct
+            // chunk c: blocks kChunkKb c .. of the I rows (and J rows off the diagonal) by direct
             // global->LDS 16-byte loads; wave v loads rows 64v .. 64v+63 of each block
             auto issue_chunk = [&](int c) {
-                uint8_t *dst = smem + (c & 1) * kChunkBytes + wv * 1024;
+                uint8_t *dst = smem + (c % kChunkBufs) * kChunkBytes + wv * 1024;
 #pragma unroll
                 for (int side = 0; side < 2; ++side) {
                     if (side && diag) break;
                     const int64_t ro = ((int64_t)(side ? bj : bi) * kSc2Tile + wv * 64 + lane) * 16;
 #pragma unroll
-                    for (int kb = 0; kb < kChunkKb; ++kb)
-                        if (c * kChunkKb + kb < nkb)
-                            __builtin_amdgcn_global_load_lds((gvoid *)(Cbit + (int64_t)(c * kChunkKb + kb) * kbs + ro),
-                                                             (lvoid *)(dst + side * kChunkSide + kb * 4096), 16, 0, 0);
+                    for (int kb = 0; kb < kChunkKb; ++kb)   // past the last block: a copy of it, not counted
+                        __builtin_amdgcn_global_load_lds((gvoid *)(Cbit + (int64_t)min(c * kChunkKb + kb, nkb - 1) * kbs + ro),
+                                                         (lvoid *)(dst + side * kChunkSide + kb * 4096), 16, 0, 0);
                 }
             };
-            if (etotal > 0) issue_chunk(0);
-            for (int c = 0; c < (etotal > 0 ? nch : 0); ++c) {
-                SC2_WAIT_BARRIER(0);   // chunk c has landed for every wave (and the edge list is written)
-                if (c + 1 < nch) issue_chunk(c + 1);
-                const uint8_t *Ib = smem + (c & 1) * kChunkBytes, *Jb = diag ? Ib : Ib + kChunkSide;
+            const int lpc = (diag ? 1 : 2) * kChunkKb;   // loads per chunk and lane
+            const int nrun = etotal > 0 ? nch : 0;
+            for (int c = 0; c < min(nrun, kChunkBufs - 1); ++c) issue_chunk(c);
+            for (int c = 0; c < nrun; ++c) {
+                // chunk c has landed once at most (chunks issued after it) x lpc loads are outstanding;
+                // the barrier also tells every wave that chunk c - 1's buffer is free
+                const int outstanding = min(kChunkBufs - 2, nrun - 1 - c) * lpc;
+                switch (outstanding) {
+                case 16: SC2_WAIT_BARRIER(16); break;
+                case 12: SC2_WAIT_BARRIER(12); break;
+                case 8: SC2_WAIT_BARRIER(8); break;
+                case 6: SC2_WAIT_BARRIER(6); break;
+                case 4: SC2_WAIT_BARRIER(4); break;
+                case 2: SC2_WAIT_BARRIER(2); break;
+                default: SC2_WAIT_BARRIER(0); break;
+                }
+                if (c + kChunkBufs - 1 < nrun) issue_chunk(c + kChunkBufs - 1);
+                const uint8_t *Ib = smem + (c % kChunkBufs) * kChunkBytes, *Jb = diag ? Ib : Ib + kChunkSide;
                 const int kbn = min(kChunkKb, nkb - c * kChunkKb);
                 int cur = -1;
                 uint4 ri[kChunkKb];
-                for (int e = e0; e < e1; ++e) {
-                    const uint32_t v = edgeL[e];
-                    const int li = v >> 8, lj = v & 255;
-                    if (li != cur) {
-                        cur = li;
+                constexpr int kU = 2;   // edges whose J rows are read together
+#pragma unroll
+                for (int k0 = 0; k0 < kEdgesPerThread; k0 += kU) {
+                    if (k0 >= ne) continue;   // (not break: the loop must unroll, the arrays stay in registers)
+                    uint4 rj[kU][kChunkKb];
+#pragma unroll
+                    for (int u = 0; u < kU; ++u)
 #pragma unroll
                         for (int kb = 0; kb < kChunkKb; ++kb)
-                            if (kb < kbn) ri[kb] = *reinterpret_cast<const uint4 *>(Ib + kb * 4096 + li * 16);
-                    }
-                    int sum = 0;
+                            rj[u][kb] = k0 + u < ne && kb < kbn
+                                            ? *reinterpret_cast<const uint4 *>(Jb + kb * 4096 + (myv[k0 + u] & 255) * 16)
+                                            : make_uint4(0, 0, 0, 0);
 #pragma unroll
-                    for (int kb = 0; kb < kChunkKb; ++kb) {
-                        if (kb < kbn) {
-                            const uint4 rj = *reinterpret_cast<const uint4 *>(Jb + kb * 4096 + lj * 16);
-                            sum += __builtin_popcount(ri[kb].x & rj.x) + __builtin_popcount(ri[kb].y & rj.y) +
-                                   __builtin_popcount(ri[kb].z & rj.z) + __builtin_popcount(ri[kb].w & rj.w);
+                    for (int u = 0; u < kU; ++u) {
+                        const int li = (int)(myv[k0 + u] >> 8);
+                        if (k0 + u < ne && li != cur) {
+                            cur = li;
+#pragma unroll
+                            for (int kb = 0; kb < kChunkKb; ++kb) ri[kb] = *reinterpret_cast<const uint4 *>(Ib + kb * 4096 + li * 16);
                         }
-                    }
-                    cntL[e] += sum;
-                }
-                __syncthreads();   // this buffer is read for the last time before chunk c + 2 lands in it
-            }
-            // this thread's edges and counts to registers; the LDS becomes the tile T (zero, then
-            // the counts scattered in; weights below 2^16)
-            uint32_t myv[32];
-            int myc[32];
+                        int sum = 0;
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                myv[k] = e0 + k < e1 ? edgeL[e0 + k] : 0u;
-                myc[k] = e0 + k < e1 ? cntL[e0 + k] : 0;
+                        for (int kb = 0; kb < kChunkKb; ++kb)
+                            sum += __builtin_popcount(ri[kb].x & rj[u][kb].x) + __builtin_popcount(ri[kb].y & rj[u][kb].y) +
+                                   __builtin_popcount(ri[kb].z & rj[u][kb].z) + __builtin_popcount(ri[kb].w & rj[u][kb].w);
+                        myc[k0 + u] += k0 + u < ne ? sum : 0;
+                    }
+                }
             }
+            // the LDS becomes the tile T (zero, then the counts scattered in; weights below 2^16)
             __syncthreads();
             for (int k = tid; k < kTileBytes / 16; k += 256) reinterpret_cast<uint4 *>(smem)[k] = make_uint4(0, 0, 0, 0);
             __syncthreads();
             int32_t *ghs = w.ghist + ((int64_t)b * kHistGroups + local % kHistGroups) * w.hist_stride;
             const bool small_hist = d.n <= kHistLdsBins;
 #pragma unroll
-            for (int k = 0; k < 32; ++k) {
-                if (e0 + k < e1) {
+            for (int k = 0; k < kEdgesPerThread; ++k) {
+                if (k < ne) {
                     T[(myv[k] >> 8) * kSc2Tile + (myv[k] & 255)] = (uint16_t)myc[k];
                     const int c = myc[k];
                     if (c > 0) {   // the weight histogram counts nonzero weights
