@@ -76,6 +76,34 @@ def test_batch_in_size_order_matches_oracle():
         r.close()
 
 
+def test_batch_of_more_pairs_than_planner_threads():
+    # 1100 small pairs: the planner walks them in two chunks of its 1024 threads, reads the order
+    # back from device memory (not its LDS copy) and deals 1100 slots to the XCDs; invalid pairs
+    # (N < 3) are mixed in. Every record and mask against the oracle, all taps for a sample.
+    rng = np.random.default_rng(7)
+    ns = [int(x) for x in rng.integers(0, 129, size=1100)]
+    ns[5] = ns[700] = 1
+    ns[1024] = 0
+    r = T.Registrar(max_n=128, max_batch=len(ns), max_k1=40, max_k2=2)
+    try:
+        pairs, src, dst, offs = make_batch(ns, 6)
+        prm = T.make_params(0.1, 0.1, k1=30, k2=2)
+        say(f"batch of {len(ns)} pairs, N 0..128")
+        out, masks = r.register_batch(to_dev(torch, src), to_dev(torch, dst), to_dev(torch, offs), prm, max_n=128)
+        torch.cuda.synchronize()
+        res = T.parse_results(out, len(ns))
+        masks = masks.cpu().numpy()
+        for b, n in enumerate(ns):
+            if n < 3:
+                assert res[b].status == T.TR_ERR_INVALID_ARG and res[b].best_hyp == -1, b
+                continue
+            X, Y = src[offs[b]:offs[b + 1]], dst[offs[b]:offs[b + 1]]
+            check_taps(r, X, Y, prm, res[b], masks[offs[b]:offs[b + 1]], pair=b, label=f"pair {b} n={n}",
+                       dense=b % 50 == 0 or b >= 1020)
+    finally:
+        r.close()
+
+
 def test_batch_equals_single(reg):
     ns = [400, 900, 128]
     pairs, src, dst, offs = make_batch(ns, 2)
