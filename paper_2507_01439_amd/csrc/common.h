@@ -253,6 +253,35 @@ __device__ __forceinline__ int stage_pair(const Work &w, int stage, int item, in
     return w.pre[kOrderRow * w.pre_stride + k];
 }
 
+// The same lookup from a copy in LDS of a stage's prefix sums and the slot order, for kernels
+// with many short items (the binary search then takes no device-memory round trips). Batches of
+// at most kSlotCacheMax pairs; the copy is made by slot_cache_fill, followed by a barrier.
+constexpr int kSlotCacheMax = 1024;
+struct SlotCache {
+    int32_t pre[kSlotCacheMax + 1];
+    int32_t order[kSlotCacheMax];
+};
+
+__device__ __forceinline__ bool slot_cache_fill(const Work &w, int stage, SlotCache &c)
+{
+    if (w.n1 || w.plan->B > kSlotCacheMax) return false;
+    const int B = w.plan->B;
+    for (int k = threadIdx.x; k <= B; k += blockDim.x) {
+        c.pre[k] = w.pre[stage * w.pre_stride + k];
+        if (k < B) c.order[k] = w.pre[kOrderRow * w.pre_stride + k];
+    }
+    return true;
+}
+
+__device__ __forceinline__ int stage_pair_cached(const Work &w, int stage, const SlotCache &c, bool cached, int item,
+                                                 int &local)
+{
+    if (!cached) return stage_pair(w, stage, item, local);
+    const int k = find_pair(c.pre, w.plan->B, item);
+    local = item - c.pre[k];
+    return c.order[k];
+}
+
 // First item of pair b in a stage's list, and its item count.
 __device__ __forceinline__ int stage_first(const Work &w, int stage, int b)
 {

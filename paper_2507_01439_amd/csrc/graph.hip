@@ -342,6 +342,9 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
     __shared__ __attribute__((aligned(16))) uint8_t tile[2][64 * kNibStride];
     __shared__ int32_t hrow[LEARNED ? 64 : 1][17], hcol[LEARNED ? 64 : 1][17];
     __shared__ int32_t red[4][3];
+    __shared__ SlotCache slots;
+    const bool cached = slot_cache_fill(w, kCompat, slots);
+    __syncthreads();
     const int total = stage_total(w, kCompat);
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid & 63, wv = tid >> 6;
     const float tau = w.tau, q = tau * 0.25f;
@@ -350,7 +353,7 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
     auto fetch = [&](int item) {
         if (tid < 128 && item < total) {
             int local;
-            const int b = stage_pair(w, kCompat, item, local);
+            const int b = stage_pair_cached(w, kCompat, slots, cached, item, local);
             const PairDesc d = pair_desc(w, b);
             int bi, bj;
             tri_decode(local, d.npad / kCompatTile, bi, bj);
@@ -369,7 +372,7 @@ __global__ void __launch_bounds__(256, 2) k_compat(Work w)
     fetch(blockIdx.x);
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int local;
-        const int b = stage_pair(w, kCompat, item, local);
+        const int b = stage_pair_cached(w, kCompat, slots, cached, item, local);
         const PairDesc d = pair_desc(w, b);
         int bi, bj;
         tri_decode(local, d.npad / kCompatTile, bi, bj);

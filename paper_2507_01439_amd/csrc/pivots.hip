@@ -252,11 +252,14 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
     __shared__ uint64_t buf[kCollectCap];
     __shared__ int32_t nbuf, base;
     __shared__ int32_t part[4];
+    __shared__ SlotCache slots;
+    const bool cached = slot_cache_fill(w, kRowBlk, slots);
+    __syncthreads();
     const int total = stage_total(w, kRowBlk);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int blk;
-        const int b = stage_pair(w, kRowBlk, item, blk);
+        const int b = stage_pair_cached(w, kRowBlk, slots, cached, item, blk);
         const PairState st = w.state[b];
         const PairDesc d = pair_desc(w, b);
         if (d.kpiv <= 0) continue;   // same for the whole workgroup
