@@ -53,10 +53,12 @@ def test_batch_uneven_matches_oracle(reg):
         check_taps(reg, X, Y, prm, r, masks[offs[b]:offs[b + 1]], pair=b, label=f"batch pair {b} n={n}")
 
 
-def test_batch_in_size_order_matches_oracle():
-    # 21 pairs (a batch large enough for the size-ordered work lists: pairs sorted by tile count
-    # and dealt to the XCDs), with sizes across several tile counts, equal sizes and invalid pairs
-    ns = [700, 2, 256, 257, 640, 3, 512, 700, 100, 0, 513, 300, 699, 64, 255, 600, 5, 450, 700, 1, 333]
+@pytest.mark.parametrize("count", [15, 16, 21])
+def test_batch_in_size_order_matches_oracle(count):
+    # 21 pairs (from 16 on, a batch takes the size-ordered work lists: pairs sorted by tile count
+    # and dealt to the XCDs; 15 keeps index order), with sizes across several tile counts, equal
+    # sizes and invalid pairs
+    ns = [700, 2, 256, 257, 640, 3, 512, 700, 100, 0, 513, 300, 699, 64, 255, 600, 5, 450, 700, 1, 333][:count]
     r = T.Registrar(max_n=700, max_batch=len(ns), max_k1=200, max_k2=2)
     try:
         pairs, src, dst, offs = make_batch([max(n, 0) for n in ns], 5)
