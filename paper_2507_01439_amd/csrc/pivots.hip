@@ -253,18 +253,51 @@ __global__ void __launch_bounds__(256) k_rowscan(Work w)
     __shared__ int32_t nbuf, base;
     __shared__ int32_t part[4];
     __shared__ SlotCache slots;
+    // batches of up to kInfoMax pairs: each slot's threshold, path and sizes in LDS as well, so an
+    // item (four rows) starts with no device-memory round trip but its rows' maxima
+    constexpr int kInfoMax = 256;
+    struct SlotInfo {
+        int32_t alpha, fast, kpiv, n, npad, pad;
+        int64_t g_off;
+    };
+    __shared__ SlotInfo info[kInfoMax];
     const bool cached = slot_cache_fill(w, kRowBlk, slots);
+    const bool with_info = cached && w.plan->B <= kInfoMax;
+    __syncthreads();
+    if (with_info)
+        for (int k = threadIdx.x; k < w.plan->B; k += blockDim.x) {
+            const int b = slots.order[k];
+            const PairState st = w.state[b];
+            const PairDesc d = w.pairs[b];
+            info[k] = SlotInfo{st.alpha, st.fast, d.kpiv, d.n, d.npad, 0, d.g_off};
+        }
     __syncthreads();
     const int total = stage_total(w, kRowBlk);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int blk;
-        const int b = stage_pair_cached(w, kRowBlk, slots, cached, item, blk);
-        const PairState st = w.state[b];
-        const PairDesc d = pair_desc(w, b);
+        int blk, b, alpha, fast;
+        PairDesc d;
+        if (with_info) {
+            const int k = find_pair(slots.pre, w.plan->B, item);
+            blk = item - slots.pre[k];
+            b = slots.order[k];
+            const SlotInfo &f = info[k];
+            alpha = f.alpha;
+            fast = f.fast;
+            d.kpiv = f.kpiv;
+            d.n = f.n;
+            d.npad = f.npad;
+            d.g_off = f.g_off;
+        } else {
+            b = stage_pair_cached(w, kRowBlk, slots, cached, item, blk);
+            const PairState st = w.state[b];
+            d = pair_desc(w, b);
+            alpha = st.alpha;
+            fast = st.fast;
+        }
         if (d.kpiv <= 0) continue;   // same for the whole workgroup
-        const bool ordered = !st.fast;
-        const int alpha = st.alpha, c1 = (d.n + 7) >> 3;
+        const bool ordered = !fast;
+        const int c1 = (d.n + 7) >> 3;
         const int i = blk * kRowsPerItem + wv;
         const int rm = i < d.n ? w.rowmax[(int64_t)b * w.max_n + i] : 0;
         const bool live = i < d.n && !(alpha > 0 && rm < alpha);
