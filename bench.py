@@ -11,7 +11,8 @@ N = 20000). Prints one JSON line: registrations/s, per-stage times from HIP
 events recorded by the library on its stream (in the layout of the paper's
 per-stage table too), the roofline of the dominant kernel, learned vs plain
 pivots at equal success rate (32 held-out hard pairs at N = 5000, or the 16
-outdoor pairs), and (indoor workloads) the CPU oracle timed on a bounded sample.
+outdoor pairs), the scorer's training throughput (indoor N = 5000), and (indoor
+workloads) the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -30,6 +31,14 @@ PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # unpacked float32 vector issue, lane
 COMPAT_SLOTS_PER_PAIR = 22.0   # minimum vector issue slots of one compatibility evaluation
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E, GB/s
 WEIGHTS = os.path.join(ROOT, "paper_2507_01439_amd", "weights", "scorer_indoor.bin")
+PEAK_FP32_TFLOPS = 157.3    # MI355X float32 vector rate (the scorer's kernels use unpacked float32 FMAs)
+# Scorer training, per sample (19 -> 64 -> 64 -> 1): multiply-adds of the forward pass (5376), of
+# the layer-2 input gradient (4096) and of the weight gradients (5376), two flops each
+MLP_TRAIN_FLOP_PER_SAMPLE = 2.0 * (5376 + 4096 + 5376)
+# HBM bytes per sample a training step cannot avoid with per-sample activations kept for the
+# weight-gradient pass: the 19 bf16 features and the label read twice, four 64-float rows
+# (activations and deltas) and two floats (delta and loss) written once and read once
+MLP_TRAIN_BYTES_PER_SAMPLE = 2.0 * (38 + 1) + 2.0 * 4 * (4 * 64 + 2)
 
 
 def kernel_source_hash():
@@ -92,6 +101,42 @@ TABLE7 = {   # the paper's per-stage table: graph construction, pivot-guided sea
 }
 
 
+def training_rate(torch, minibatch=65536, steps=20, warmup=3):
+    """Scorer training throughput: tr_train_step (forward, backward, weight-gradient reduction,
+    Adam) on minibatches of features of generated indoor pairs (N ~ U{1000..5000}, inlier ratio
+    ~ U[2 %, 30 %], the training recipe), timed with events on the current stream, against the
+    float32 vector roof and the HBM roof of its per-sample traffic."""
+    from paper_2507_01439_amd import train_scorer
+    from paper_2507_01439_amd import turboreg as T
+    treg = T.Registrar(max_n=5000, max_batch=32, max_k1=1, max_k2=1)
+    try:
+        T.tr_scorer_set(treg.h, train_scorer.init_params(1))
+        feat, labels = train_scorer.build_features(treg, torch, 32, 32, 5, lambda s: None)
+        m = min(minibatch, feat.shape[0])
+        xb, yb = feat[:m].contiguous(), labels[:m].contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        for _ in range(warmup):
+            T.tr_train_step(treg.h, xb, yb, m, 1e-3, loss)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            T.tr_train_step(treg.h, xb, yb, m, 1e-3, loss)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+    finally:
+        treg.close()
+    rate = m / (ms * 1e-3)
+    tflops = rate * MLP_TRAIN_FLOP_PER_SAMPLE / 1e12
+    gbs = rate * MLP_TRAIN_BYTES_PER_SAMPLE / 1e9
+    return {"samples_per_s": rate, "minibatch": m, "ms_per_step": ms, "steps": steps,
+            "flop_per_sample": MLP_TRAIN_FLOP_PER_SAMPLE, "achieved_tflops": tflops,
+            "fp32_vector_frac": tflops / PEAK_FP32_TFLOPS, "bytes_per_sample": MLP_TRAIN_BYTES_PER_SAMPLE,
+            "achieved_gbs": gbs, "hbm_frac": gbs / PEAK_HBM_GBS,
+            "kernels": "k_mlp_fwdbwd, k_mlp_wgrad, k_mlp_reduce, k_adam per step"}
+
+
 def workload(name):
     from paper_2507_01439_amd import synth
     if name in ("indoor_n5000", "indoor_n1000"):
@@ -119,6 +164,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain comparison at equal success rate (indoor N = 5000 and outdoor16)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--no-training", action="store_true",
+                    help="skip the scorer-training throughput (indoor N = 5000 only)")
     ap.add_argument("--concurrent", type=int, default=2, metavar="K",
                     help="also time single-pair registrations spread over K handles on K streams (0: skip)")
     ap.add_argument("--ranking", action="store_true",
@@ -335,6 +382,8 @@ def main():
             T.tr_scorer_load(lreg.h, f.read())
         line["learned_vs_plain"] = eval_learned.compare(lreg, torch, pairs, k1_sweep=sweep, ref_k1=ref)
         lreg.close()
+    if not args.no_training and args.workload == "indoor_n5000":
+        line["scorer_training"] = training_rate(torch)
     if args.cpu_budget > 0 and args.workload in ("indoor_n5000", "indoor_n1000"):
         line["cpu_baseline"] = cpu_baseline([g[0] for g in groups], cfg, args.cpu_budget)
     reg.close()

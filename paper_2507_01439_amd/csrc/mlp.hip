@@ -540,6 +540,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const uint16_t *feat, const 
 
 constexpr int kTile = 256;   // samples per weight-gradient work item
 constexpr int kSub = 32;     // samples staged in LDS at a time
+constexpr int kSubPad = kSub + 1;   // LDS row stride: the rows a wave reads at one sample fall in distinct banks
 
 // Partial sums over one tile of samples of every gradient (and the loss).
 // Thread t owns a 4 x 4 block of dW2, up to 5 entries of dW1 and one of the
@@ -547,27 +548,49 @@ constexpr int kSub = 32;     // samples staged in LDS at a time
 __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t m, const float *scratch,
                                                    float *partial)
 {
-    __shared__ float sa1[64][kSub], sa2[64][kSub], sd1[64][kSub], sd2[64][kSub], sx[19][kSub], sds[kSub], sls[kSub];
+    __shared__ float sa1[64][kSubPad], sa2[64][kSubPad], sd1[64][kSubPad], sd2[64][kSubPad], sx[19][kSubPad], sds[kSub],
+        sls[kSub];
     const Scratch S = scratch_view(const_cast<float *>(scratch), m);
     const int t = threadIdx.x;
     const int o2 = 4 * (t >> 4), k2 = 4 * (t & 15);
     const int o1 = t >> 2, kg = t & 3;
     const int64_t n0 = (int64_t)blockIdx.x * kTile;
     float g2[4][4] = {}, g1[5] = {}, gv = 0.0f;
-    for (int sub = 0; sub < kTile; sub += kSub) {
-        for (int idx = t; idx < 64 * kSub; idx += 256) {
-            const int f = idx / kSub, c = idx % kSub;
+    // staging: thread t moves entries idx = t + 256 u (u < kStageIt) of each kSub-sample block,
+    // row f = idx / kSub, sample c = idx % kSub; a block's loads are all issued into registers
+    // before any is used, and the next block's while the current one is summed
+    constexpr int kStageIt = 64 * kSub / 256;
+    float va1[kStageIt], va2[kStageIt], vd1[kStageIt], vd2[kStageIt], vx[kStageIt], vq = 0.0f;
+    auto fetch = [&](int sub) {
+#pragma unroll
+        for (int u = 0; u < kStageIt; ++u) {
+            const int idx = t + 256 * u, f = idx / kSub, c = idx % kSub;
             const int64_t n = n0 + sub + c;
             const bool ok = n < m;
-            sa1[f][c] = ok ? S.a1[f * m + n] : 0.0f;
-            sa2[f][c] = ok ? S.a2[f * m + n] : 0.0f;
-            sd1[f][c] = ok ? S.d1[f * m + n] : 0.0f;
-            sd2[f][c] = ok ? S.d2[f * m + n] : 0.0f;
-            if (f < 19) sx[f][c] = ok ? bf2f(feat[n * 19 + f]) : 0.0f;
-            if (f == 19) sds[c] = ok ? S.ds[n] : 0.0f;
-            if (f == 20) sls[c] = ok ? S.ls[n] : 0.0f;
+            va1[u] = ok ? S.a1[f * m + n] : 0.0f;
+            va2[u] = ok ? S.a2[f * m + n] : 0.0f;
+            vd1[u] = ok ? S.d1[f * m + n] : 0.0f;
+            vd2[u] = ok ? S.d2[f * m + n] : 0.0f;
+            vx[u] = ok && f < 19 ? bf2f(feat[n * 19 + f]) : 0.0f;
+            if (f == 19) vq = ok ? S.ds[n] : 0.0f;   // rows 19 and 20 (delta, loss) fall to different threads
+            if (f == 20) vq = ok ? S.ls[n] : 0.0f;
+        }
+    };
+    fetch(0);
+    for (int sub = 0; sub < kTile; sub += kSub) {
+#pragma unroll
+        for (int u = 0; u < kStageIt; ++u) {
+            const int idx = t + 256 * u, f = idx / kSub, c = idx % kSub;
+            sa1[f][c] = va1[u];
+            sa2[f][c] = va2[u];
+            sd1[f][c] = vd1[u];
+            sd2[f][c] = vd2[u];
+            if (f < 19) sx[f][c] = vx[u];
+            if (f == 19) sds[c] = vq;
+            if (f == 20) sls[c] = vq;
         }
         __syncthreads();
+        if (sub + kSub < kTile) fetch(sub + kSub);
         for (int c = 0; c < kSub; ++c) {
 #pragma unroll
             for (int a = 0; a < 4; ++a)
@@ -599,13 +622,22 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t
     else if (t == 193) out[TR_MLP_NPARAM] = gv;
 }
 
-// Sum the tiles' partials in tile order (deterministic).
+// Sum the tiles' partials in tile order (deterministic); the loads of kReduceBatch tiles are
+// issued together, then added one after another.
+constexpr int kReduceBatch = 32;
 __global__ void __launch_bounds__(256) k_mlp_reduce(const float *partial, int64_t tiles, float *grads, float *loss)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= kGradSlots) return;
     float acc = 0.0f;
-    for (int64_t t = 0; t < tiles; ++t) acc += partial[t * kGradSlots + p];
+    for (int64_t t0 = 0; t0 < tiles; t0 += kReduceBatch) {
+        float v[kReduceBatch];
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u) v[u] = t0 + u < tiles ? partial[(t0 + u) * kGradSlots + p] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < kReduceBatch; ++u)
+            if (t0 + u < tiles) acc += v[u];
+    }
     if (p < TR_MLP_NPARAM) grads[p] = acc;
     else if (loss) *loss = acc;
 }
