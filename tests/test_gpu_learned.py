@@ -105,11 +105,13 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def test_mlp_gradients_match_oracle(reg):
+# 2048: whole 256-sample tiles; 2125: a last tile of 77 samples (a partial 32-sample block, then
+# empty blocks); 9000: 36 tiles, so the tile reduction runs one full batch of 32 tiles and a partial one
+@pytest.mark.parametrize("m", [2048, 2125, 9000])
+def test_mlp_gradients_match_oracle(reg, m):
     params = rand_params(3)
     T.tr_scorer_set(reg.h, params)
     rng = np.random.default_rng(4)
-    m = 2048
     F = rng.random((m, 19)).astype(np.float32)
     y = (rng.random(m) < 0.3).astype(np.uint8)
     bits = (bf16(F).view(np.uint32) >> 16).astype(np.uint16)
