@@ -461,21 +461,34 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const uint16_t *feat, int64
 
 // Scratch layout, feature-major so that consecutive samples are consecutive:
 //   A1[64][m], A2[64][m], D1[64][m], D2[64][m], DS[m], LS[m]
+constexpr int kTile = 256;   // samples per weight-gradient work item
+constexpr int kSub = 32;     // samples staged in LDS at a time
+constexpr int kSubPad = kSub + 1;   // LDS row stride: the rows a wave reads at one sample fall in distinct banks
+
+// Per-sample rows of the backward pass, tile-major: the 64 entries of sample n in one of the four
+// arrays are at at(f, n), f < 64, so the kTile samples of a weight-gradient work item occupy one
+// contiguous block of 64 x kTile floats per array (consecutive samples stay consecutive).
 struct Scratch {
     float *a1, *a2, *d1, *d2, *ds, *ls;
-    int64_t m;
+    __device__ __forceinline__ int64_t at(int f, int64_t n) const
+    {
+        return (n / kTile) * (64 * kTile) + f * kTile + n % kTile;
+    }
 };
+
+// Samples the scratch holds for m: whole tiles.
+__host__ __device__ __forceinline__ int64_t scratch_samples(int64_t m) { return (m + kTile - 1) / kTile * kTile; }
 
 __device__ __forceinline__ Scratch scratch_view(float *base, int64_t m)
 {
+    const int64_t mp = scratch_samples(m);
     Scratch s;
     s.a1 = base;
-    s.a2 = base + 64 * m;
-    s.d1 = base + 128 * m;
-    s.d2 = base + 192 * m;
-    s.ds = base + 256 * m;
-    s.ls = base + 257 * m;
-    s.m = m;
+    s.a2 = base + 64 * mp;
+    s.d1 = base + 128 * mp;
+    s.d2 = base + 192 * mp;
+    s.ds = base + 256 * mp;
+    s.ls = base + 257 * mp;
     return s;
 }
 
@@ -501,7 +514,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const uint16_t *feat, const 
 #pragma unroll
             for (int k = 0; k < 19; ++k) acc = __builtin_fmaf(L.p[kW1 + 19 * o + k], x[k], acc);
             a1[o] = bfround(gelu(acc));
-            S.d1[o * m + n] = gelu_grad(acc);
+            S.d1[S.at(o, n)] = gelu_grad(acc);
         }
         float s = L.p[kB3];
 #pragma unroll 2
@@ -510,12 +523,12 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const uint16_t *feat, const 
 #pragma unroll
             for (int k = 0; k < 64; ++k) acc = __builtin_fmaf(L.p[kW2 + 64 * o + k], a1[k], acc);
             const float a = bfround(gelu(acc));
-            S.a2[o * m + n] = a;
-            S.d2[o * m + n] = gelu_grad(acc);
+            S.a2[S.at(o, n)] = a;
+            S.d2[S.at(o, n)] = gelu_grad(acc);
             s = __builtin_fmaf(L.p[kW3 + o], a, s);
         }
 #pragma unroll
-        for (int o = 0; o < 64; ++o) S.a1[o * m + n] = a1[o];
+        for (int o = 0; o < 64; ++o) S.a1[S.at(o, n)] = a1[o];
         // loss and backward
         const float y = labels[n] ? 1.0f : 0.0f;
         const float loss = fmaxf(s, 0.0f) - s * y + log1pf(expf(-fabsf(s)));
@@ -523,24 +536,20 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const uint16_t *feat, const 
         float d2[64];
 #pragma unroll
         for (int o = 0; o < 64; ++o) {
-            d2[o] = ds * L.p[kW3 + o] * S.d2[o * m + n];
-            S.d2[o * m + n] = d2[o];
+            d2[o] = ds * L.p[kW3 + o] * S.d2[S.at(o, n)];
+            S.d2[S.at(o, n)] = d2[o];
         }
 #pragma unroll 2
         for (int k = 0; k < 64; ++k) {
             float acc = 0.0f;
 #pragma unroll
             for (int o = 0; o < 64; ++o) acc = __builtin_fmaf(L.p[kW2 + 64 * o + k], d2[o], acc);
-            S.d1[k * m + n] = acc * S.d1[k * m + n];
+            S.d1[S.at(k, n)] = acc * S.d1[S.at(k, n)];
         }
         S.ds[n] = ds;
         S.ls[n] = loss * inv_m;
     }
 }
-
-constexpr int kTile = 256;   // samples per weight-gradient work item
-constexpr int kSub = 32;     // samples staged in LDS at a time
-constexpr int kSubPad = kSub + 1;   // LDS row stride: the rows a wave reads at one sample fall in distinct banks
 
 // Partial sums over one tile of samples of every gradient (and the loss).
 // Thread t owns a 4 x 4 block of dW2, up to 5 entries of dW1 and one of the
@@ -567,10 +576,10 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t
             const int idx = t + 256 * u, f = idx / kSub, c = idx % kSub;
             const int64_t n = n0 + sub + c;
             const bool ok = n < m;
-            va1[u] = ok ? S.a1[f * m + n] : 0.0f;
-            va2[u] = ok ? S.a2[f * m + n] : 0.0f;
-            vd1[u] = ok ? S.d1[f * m + n] : 0.0f;
-            vd2[u] = ok ? S.d2[f * m + n] : 0.0f;
+            va1[u] = ok ? S.a1[S.at(f, n)] : 0.0f;
+            va2[u] = ok ? S.a2[S.at(f, n)] : 0.0f;
+            vd1[u] = ok ? S.d1[S.at(f, n)] : 0.0f;
+            vd2[u] = ok ? S.d2[S.at(f, n)] : 0.0f;
             vx[u] = ok && f < 19 ? bf2f(feat[n * 19 + f]) : 0.0f;
             if (f == 19) vq = ok ? S.ds[n] : 0.0f;   // rows 19 and 20 (delta, loss) fall to different threads
             if (f == 20) vq = ok ? S.ls[n] : 0.0f;
@@ -675,7 +684,7 @@ hipError_t ensure_scratch(MlpState *s, int64_t m)
         if (s->scratch) hipFree(s->scratch);
         s->scratch = nullptr;
         s->scratch_m = 0;
-        hipError_t e = hipMalloc(&s->scratch, sizeof(float) * 258 * (size_t)m);
+        hipError_t e = hipMalloc(&s->scratch, sizeof(float) * 258 * (size_t)scratch_samples(m));
         if (e != hipSuccess) return e;
         s->scratch_m = m;
     }
