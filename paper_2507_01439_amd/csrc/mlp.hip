@@ -551,20 +551,25 @@ __global__ void __launch_bounds__(256) k_mlp_fwdbwd(const uint16_t *feat, const 
     }
 }
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
 // Partial sums over one tile of samples of every gradient (and the loss).
-// Thread t owns a 4 x 4 block of dW2, up to 5 entries of dW1 and one of the
-// vectors (db1, db2, dW3, db3, loss); samples are summed in index order.
+// The weight gradients are contractions over the samples: dW2 = D2^T A1 and
+// dW1 = D1^T X on float32 MFMA (32 x 32 x 2, float32 products and sums): wave
+// w owns the 32 x 32 block (w / 2, w % 2) of dW2, waves 0 and 1 also the rows
+// 32 w .. 32 w + 31 of dW1 (19 of 32 columns used). Thread t also sums one of
+// the vectors (db1, db2, dW3, db3, loss) in sample order.
 __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t m, const float *scratch,
                                                    float *partial)
 {
     __shared__ float sa1[64][kSubPad], sa2[64][kSubPad], sd1[64][kSubPad], sd2[64][kSubPad], sx[19][kSubPad], sds[kSub],
         sls[kSub];
     const Scratch S = scratch_view(const_cast<float *>(scratch), m);
-    const int t = threadIdx.x;
-    const int o2 = 4 * (t >> 4), k2 = 4 * (t & 15);
-    const int o1 = t >> 2, kg = t & 3;
+    const int t = threadIdx.x, w = t >> 6, li = t & 31, lk = (t >> 5) & 1;
+    const int ob = w >> 1, kb = w & 1;   // this wave's dW2 block: rows 32 ob.., columns 32 kb..
     const int64_t n0 = (int64_t)blockIdx.x * kTile;
-    float g2[4][4] = {}, g1[5] = {}, gv = 0.0f;
+    v16f acc2 = {}, acc1 = {};
+    float gv = 0.0f;
     // staging: thread t moves entries idx = t + 256 u (u < kStageIt) of each kSub-sample block,
     // row f = idx / kSub, sample c = idx % kSub; a block's loads are all issued into registers
     // before any is used, and the next block's while the current one is summed
@@ -600,14 +605,17 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t
         }
         __syncthreads();
         if (sub + kSub < kTile) fetch(sub + kSub);
+        // two samples per MFMA: lane (li, lk) supplies row li of the A block and column li of the
+        // B block at sample c0 + lk
+#pragma unroll
+        for (int c0 = 0; c0 < kSub; c0 += 2) {
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x2f32(sd2[32 * ob + li][c0 + lk], sa1[32 * kb + li][c0 + lk], acc2, 0,
+                                                        0, 0);
+            if (w < 2)
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sd1[32 * w + li][c0 + lk], li < 19 ? sx[li][c0 + lk] : 0.0f,
+                                                            acc1, 0, 0, 0);
+        }
         for (int c = 0; c < kSub; ++c) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) g2[a][e] = __builtin_fmaf(sd2[o2 + a][c], sa1[k2 + e][c], g2[a][e]);
-#pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (kg + 4 * q < 19) g1[q] = __builtin_fmaf(sd1[o1][c], sx[kg + 4 * q][c], g1[q]);
             if (t < 64) gv += sd1[t][c];
             else if (t < 128) gv += sd2[t - 64][c];
             else if (t < 192) gv = __builtin_fmaf(sds[c], sa2[t - 128][c], gv);
@@ -617,13 +625,13 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t
         __syncthreads();
     }
     float *out = partial + (int64_t)blockIdx.x * kGradSlots;
+    // block entry (i, j) of register r in lane (li, lk): i = 8 (r / 4) + 4 lk + r % 4, j = li
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[kW2 + 64 * (o2 + a) + k2 + e] = g2[a][e];
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-        if (kg + 4 * q < 19) out[kW1 + 19 * o1 + kg + 4 * q] = g1[q];
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * lk + (r & 3);
+        out[kW2 + 64 * (32 * ob + i) + 32 * kb + li] = acc2[r];
+        if (w < 2 && li < 19) out[kW1 + 19 * (32 * w + i) + li] = acc1[r];
+    }
     if (t < 64) out[kB1 + t] = gv;
     else if (t < 128) out[kB2 + t - 64] = gv;
     else if (t < 192) out[kW3 + t - 128] = gv;
