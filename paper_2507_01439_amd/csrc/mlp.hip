@@ -615,12 +615,23 @@ __global__ void __launch_bounds__(256) k_mlp_wgrad(const uint16_t *feat, int64_t
                 acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(sd1[32 * w + li][c0 + lk], li < 19 ? sx[li][c0 + lk] : 0.0f,
                                                             acc1, 0, 0, 0);
         }
-        for (int c = 0; c < kSub; ++c) {
-            if (t < 64) gv += sd1[t][c];
-            else if (t < 128) gv += sd2[t - 64][c];
-            else if (t < 192) gv = __builtin_fmaf(sds[c], sa2[t - 128][c], gv);
-            else if (t == 192) gv += sds[c];
-            else if (t == 193) gv += sls[c];
+        // the vector sums, one per thread, over the block's samples in order (the branch is taken
+        // once per block, so each thread's reads are issued together)
+        if (t < 64) {
+#pragma unroll
+            for (int c = 0; c < kSub; ++c) gv += sd1[t][c];
+        } else if (t < 128) {
+#pragma unroll
+            for (int c = 0; c < kSub; ++c) gv += sd2[t - 64][c];
+        } else if (t < 192) {
+#pragma unroll
+            for (int c = 0; c < kSub; ++c) gv = __builtin_fmaf(sds[c], sa2[t - 128][c], gv);
+        } else if (t == 192) {
+#pragma unroll
+            for (int c = 0; c < kSub; ++c) gv += sds[c];
+        } else if (t == 193) {
+#pragma unroll
+            for (int c = 0; c < kSub; ++c) gv += sls[c];
         }
         __syncthreads();
     }
