@@ -459,8 +459,8 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const uint16_t *feat, int64
 
 // ---------------------------------------------------------------- training
 
-// Scratch layout, feature-major so that consecutive samples are consecutive:
-//   A1[64][m], A2[64][m], D1[64][m], D2[64][m], DS[m], LS[m]
+// Scratch of a training step, for m samples rounded up to whole tiles (mp): A1, A2, D1, D2
+// (64 floats per sample each, tile-major as Scratch::at places them), then DS[mp] and LS[mp].
 constexpr int kTile = 256;   // samples per weight-gradient work item
 constexpr int kSub = 32;     // samples staged in LDS at a time
 constexpr int kSubPad = kSub + 1;   // LDS row stride: the rows a wave reads at one sample fall in distinct banks
